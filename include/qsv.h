@@ -1,0 +1,199 @@
+/*
+ * qsv.h -- C ABI of libqsv: batched state-vector simulation of parameterised
+ * quantum circuits on one AMD Instinct MI355X (gfx950), with Pauli-Z readout
+ * and adjoint gradients.
+ *
+ * What is computed (the paper's problem statement, sections "State Vector
+ * Simulation", "Hybrid Machine Learning" and "Concept of Shapes"): a circuit
+ * of W qubits is a list of gates; every sample b of a batch starts in
+ * |0...0>, has the gates applied in order, and is read out as
+ * E[b,i] = <psi_b| Z_i |psi_b>. Gate angles come from a shared weight vector
+ * (trainable layers) or from a per-sample input row (embedding layers).
+ *
+ * Conventions:
+ *  - MSb-0 ordering (section "Symbols"): qubit w is bit (W-1-w) of a
+ *    basis-state index.
+ *  - Rotations R_d(theta) = exp(-i theta sigma_d / 2) (Eq. (1) for d = x):
+ *    RX = [[c,-is],[-is,c]], RY = [[c,-s],[s,c]], RZ = diag(e^{-i t/2}, e^{i t/2})
+ *    with c = cos(theta/2), s = sin(theta/2). H = (X+Z)/sqrt2. CNOT(c,t) flips
+ *    t where c = 1; CZ(a,b) negates where both are 1; CRX(c,t) applies RX to t
+ *    where c = 1. For 2-qubit gates q0 is the control, q1 the target.
+ *  - State layout: sample-major (B, 2^W) complex64, interleaved (re, im) float
+ *    pairs; amplitude idx of sample b at float offset 2 * (b * 2^W + idx).
+ *  - Expectations and gradients are float64; amplitudes and gate arithmetic
+ *    are float32.
+ *
+ * Ownership: every d_ pointer is device memory owned by the caller; the
+ * library never frees it. A plan owns its host tables and the device copies
+ * it makes of them (created on first use on a device, freed by
+ * qsv_plan_destroy). Workspaces are caller memory of at least
+ * qsv_workspace_size() bytes, 256-byte aligned.
+ *
+ * Asynchrony: qsv_forward / qsv_expval / qsv_backward validate on the host,
+ * then enqueue kernels on `stream` (a hipStream_t, NULL = default stream)
+ * and return; faults show at the caller's next synchronisation. On a
+ * non-zero return nothing was enqueued.
+ *
+ * Errors: functions return 0 or a negative QSV_ERR_* code; qsv_last_error()
+ * gives a thread-local message for the last failure in this thread.
+ *
+ * Thread safety: a plan is immutable after creation except for its lazily
+ * created per-device tables, which are guarded by a lock. Concurrent calls
+ * on one plan are safe when they use distinct workspaces and outputs.
+ */
+#ifndef QSV_H_INCLUDED
+#define QSV_H_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* gate kinds */
+enum {
+    QSV_H = 0, QSV_X = 1, QSV_Y = 2, QSV_Z = 3,
+    QSV_RX = 4, QSV_RY = 5, QSV_RZ = 6,
+    QSV_CNOT = 7, QSV_CZ = 8, QSV_CRX = 9
+};
+
+/* where a gate's angle comes from */
+enum { QSV_SRC_NONE = 0, QSV_SRC_WEIGHT = 1, QSV_SRC_INPUT = 2 };
+
+/* return codes */
+enum {
+    QSV_OK = 0,
+    QSV_ERR_ARG = -1,      /* null pointer, batch <= 0, workspace too small, bad option */
+    QSV_ERR_QUBIT = -2,    /* qubit index out of range, or a 2-qubit gate on one qubit */
+    QSV_ERR_GATE = -3,     /* unknown gate kind */
+    QSV_ERR_PARAM = -4,    /* angle source / index invalid for the gate */
+    QSV_ERR_TOO_BIG = -5,  /* W > QSV_MAX_QUBITS or the state size overflows */
+    QSV_ERR_OOM = -6,      /* host or device allocation failed */
+    QSV_ERR_HIP = -7,      /* a HIP runtime call failed; see qsv_last_error() */
+    QSV_ERR_HANDLE = -8    /* null or destroyed plan */
+};
+
+#define QSV_MAX_QUBITS 30
+
+/* methods */
+enum {
+    QSV_METHOD_FUSED = 0,   /* circuit splitting + register/LDS tiles (default) */
+    QSV_METHOD_PER_GATE = 1 /* the plain method: one strided sweep of the state per gate */
+};
+
+/* workspace queries */
+enum { QSV_OP_FORWARD = 0, QSV_OP_EXPVAL = 1, QSV_OP_BACKWARD = 2 };
+
+typedef struct {
+    int32_t kind;  /* QSV_H ... QSV_CRX */
+    int32_t q0;    /* qubit (1-qubit gates) or control (2-qubit gates) */
+    int32_t q1;    /* target of a 2-qubit gate; -1 for 1-qubit gates */
+    int32_t src;   /* QSV_SRC_NONE | QSV_SRC_WEIGHT | QSV_SRC_INPUT */
+    int32_t idx;   /* weights[idx] or inputs[b * n_inputs + idx]; -1 if src is NONE */
+} qsv_gate;
+
+typedef struct {
+    int32_t method;      /* QSV_METHOD_FUSED or QSV_METHOD_PER_GATE */
+    int32_t fuse_width;  /* k: max qubits of a splitter block (section "Circuit
+                            Splitting" suggests 3..6); 1..16 */
+    int32_t tile_qubits; /* m: qubits of one tile of amplitudes held by a
+                            workgroup, 4..12; clamped to W */
+    int32_t low_qubits;  /* c: number of lowest-stride qubits every tile keeps
+                            (contiguous runs of 2^c amplitudes); 0..m-1 */
+    int32_t max_pass_grads; /* cap on parametric gates per backward pass, 1..256 */
+    int32_t reserved[3];
+} qsv_opts;
+
+typedef struct {
+    int32_t n_qubits, n_gates, n_weights, n_inputs;
+    int32_t method, fuse_width, tile_qubits, low_qubits;
+    int32_t n_prefix_gates;   /* leading 1-qubit gates folded into the product-state init */
+    int32_t n_blocks;         /* splitter blocks over the whole gate list */
+    int32_t n_fwd_passes;     /* state sweeps of a forward (fused: tiles; per-gate: gates) */
+    int32_t n_bwd_passes;     /* sweeps of a backward */
+    int32_t n_fwd_stages;     /* register stages over all forward passes (fused) */
+    int32_t n_bwd_stages;
+    int32_t n_param_gates;    /* gates with src != NONE */
+    int32_t n_recipes;        /* cached gate-matrix products evaluated per call */
+} qsv_plan_info;
+
+typedef struct qsv_plan_s qsv_plan_t;
+
+/* Fill *opts with the defaults (fused, k = 5, m = 12, c = 5, 256). */
+void qsv_default_opts(qsv_opts* opts);
+
+/*
+ * Build a plan for a circuit (host only; no device work, no GPU needed).
+ * The plan is the gate-matrix cache of section "Gate Matrix Caching" (each
+ * gate kept as constant partial matrices plus coefficient functions of its
+ * angle, never expanded by Kronecker products) and the split of section
+ * "Circuit Splitting" (dependency-graph blocks of at most k qubits, packed
+ * into passes over tiles of the state).
+ * gates: n_gates entries, host memory, read during the call only.
+ * n_weights / n_inputs: lengths of the weight vector and of one input row.
+ * opts: NULL for defaults. *out receives the plan.
+ */
+int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n_weights,
+             int32_t n_inputs, const qsv_opts* opts, qsv_plan_t** out);
+
+/* Release a plan and its device tables. NULL is ignored. */
+void qsv_plan_destroy(qsv_plan_t* plan);
+
+/* Bytes of workspace one call of kind `op` (QSV_OP_*) needs at this batch size. */
+size_t qsv_workspace_size(const qsv_plan_t* plan, int64_t batch, int32_t op);
+
+/*
+ * Forward: d_state[b] = U_N ... U_1 |0...0> for b < batch.
+ * d_weights: n_weights float32 (may be NULL if n_weights == 0).
+ * d_inputs:  batch x n_inputs float32, row-major (may be NULL if n_inputs == 0).
+ * d_state:   batch x 2^W complex64, written.
+ */
+int qsv_forward(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
+                int64_t batch, void* d_state, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Readout (the measurement layer of section "Hybrid Machine Learning"):
+ * d_out[b * W + i] = sum_idx |psi_b[idx]|^2 (1 - 2 bit_{W-1-i}(idx)), float64.
+ * Per-thread float32 partials over at most 16 amplitudes, float64 above.
+ */
+int qsv_expval(const qsv_plan_t* plan, const void* d_state, int64_t batch, double* d_out,
+               void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint backward of L = sum_{b,i} g[b,i] E[b,i], g = d_grad_out (batch x W
+ * float64). d_state holds psi_N from qsv_forward with the same weights and
+ * inputs; it is read, not modified. Going back over the gates, the angle
+ * derivative of gate k is Im <lambda_k| P_k |psi_k> with lambda = (sum_i g_i
+ * Z_i) psi_N and P_k the gate's generator; psi and lambda are then multiplied
+ * by U_k^dagger (uncomputed) instead of being stored per gate.
+ * d_grad_weights: n_weights float64, overwritten (summed over the batch).
+ * d_grad_inputs:  batch x n_inputs float64, overwritten; may be NULL.
+ */
+int qsv_backward(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
+                 int64_t batch, const void* d_state, const double* d_grad_out,
+                 void* d_ws, size_t ws_bytes, double* d_grad_weights,
+                 double* d_grad_inputs, void* stream);
+
+/* Host-side introspection (no GPU needed). */
+int qsv_plan_get_info(const qsv_plan_t* plan, qsv_plan_info* info);
+
+/*
+ * Gate order in which a forward (which = 0) or backward (which = 1) applies
+ * the gates: order[j] is the index of the j-th gate applied (for the
+ * backward, the j-th gate uncomputed). Every gate appears once. order has
+ * n_gates entries.
+ */
+int qsv_plan_gate_order(const qsv_plan_t* plan, int32_t which, int32_t* order);
+
+/* Splitter block of every gate (blocks numbered in execution order). */
+int qsv_plan_gate_blocks(const qsv_plan_t* plan, int32_t* block_of_gate);
+
+const char* qsv_strerror(int code);
+const char* qsv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_H_INCLUDED */

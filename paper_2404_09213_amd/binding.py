@@ -1,0 +1,281 @@
+"""ctypes binding of libqsv (the C ABI declared in include/qsv.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of libqsv. The functions keep the C names (qsv_plan, qsv_forward,
+qsv_expval, qsv_backward, ...); :class:`Plan` is a small owner object around a
+plan handle that allocates workspaces with torch and passes device pointers
+and the current HIP stream.
+
+If the shared library has not been built, importing works but every call
+raises -- there is no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+
+KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "CZ": 8, "CRX": 9}
+SRC = {"none": 0, "weight": 1, "input": 2}
+METHOD = {"fused": 0, "per_gate": 1}
+OP_FORWARD, OP_EXPVAL, OP_BACKWARD = 0, 1, 2
+
+ERR_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_QUBIT", -3: "QSV_ERR_GATE",
+             -4: "QSV_ERR_PARAM", -5: "QSV_ERR_TOO_BIG", -6: "QSV_ERR_OOM", -7: "QSV_ERR_HIP",
+             -8: "QSV_ERR_HANDLE"}
+
+
+class QsvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class qsv_gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("src", ctypes.c_int32), ("idx", ctypes.c_int32)]
+
+
+class qsv_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("fuse_width", ctypes.c_int32),
+                ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
+                ("max_pass_grads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class qsv_plan_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "n_qubits", "n_gates", "n_weights", "n_inputs", "method", "fuse_width", "tile_qubits",
+        "low_qubits", "n_prefix_gates", "n_blocks", "n_fwd_passes", "n_bwd_passes",
+        "n_fwd_stages", "n_bwd_stages", "n_param_gates", "n_recipes")]
+
+
+EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_destroy", "qsv_workspace_size",
+           "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
+           "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_strerror", "qsv_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libqsv.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"libqsv.so not found at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.qsv_default_opts.argtypes = [ctypes.POINTER(qsv_opts)]
+        L.qsv_default_opts.restype = None
+        L.qsv_plan.argtypes = [i32, ctypes.POINTER(qsv_gate), i32, i32, i32,
+                               ctypes.POINTER(qsv_opts), ctypes.POINTER(vp)]
+        L.qsv_plan.restype = ctypes.c_int
+        L.qsv_plan_destroy.argtypes = [vp]
+        L.qsv_plan_destroy.restype = None
+        L.qsv_workspace_size.argtypes = [vp, i64, i32]
+        L.qsv_workspace_size.restype = sz
+        L.qsv_forward.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+        L.qsv_forward.restype = ctypes.c_int
+        L.qsv_expval.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+        L.qsv_expval.restype = ctypes.c_int
+        L.qsv_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp, vp, vp]
+        L.qsv_backward.restype = ctypes.c_int
+        L.qsv_plan_get_info.argtypes = [vp, ctypes.POINTER(qsv_plan_info)]
+        L.qsv_plan_get_info.restype = ctypes.c_int
+        L.qsv_plan_gate_order.argtypes = [vp, i32, vp]
+        L.qsv_plan_gate_order.restype = ctypes.c_int
+        L.qsv_plan_gate_blocks.argtypes = [vp, vp]
+        L.qsv_plan_gate_blocks.restype = ctypes.c_int
+        L.qsv_strerror.argtypes = [ctypes.c_int]
+        L.qsv_strerror.restype = ctypes.c_char_p
+        L.qsv_last_error.argtypes = []
+        L.qsv_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise QsvError(rc, lib().qsv_last_error().decode())
+    return rc
+
+
+# -- thin wrappers with the C names ------------------------------------------------
+
+def qsv_default_opts():
+    o = qsv_opts()
+    lib().qsv_default_opts(ctypes.byref(o))
+    return o
+
+
+def qsv_plan(n_qubits, gates, n_weights, n_inputs, opts=None):
+    """gates: sequence of (kind, q0, q1, src, idx) with kind/src as names or codes."""
+    n = len(gates)
+    arr = (qsv_gate * max(n, 1))()
+    for i, (k, q0, q1, s, idx) in enumerate(gates):
+        arr[i] = qsv_gate(KIND[k] if isinstance(k, str) else int(k), int(q0), int(q1),
+                          SRC[s] if isinstance(s, str) else int(s), int(idx))
+    h = ctypes.c_void_p()
+    _check(lib().qsv_plan(int(n_qubits), arr, n, int(n_weights), int(n_inputs),
+                          ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
+    return h
+
+
+def qsv_plan_destroy(h):
+    lib().qsv_plan_destroy(h)
+
+
+def qsv_workspace_size(h, batch, op):
+    return int(lib().qsv_workspace_size(h, int(batch), int(op)))
+
+
+def qsv_forward(h, d_weights, d_inputs, batch, d_state, d_ws, ws_bytes, stream):
+    return _check(lib().qsv_forward(h, d_weights, d_inputs, int(batch), d_state, d_ws,
+                                    int(ws_bytes), stream))
+
+
+def qsv_expval(h, d_state, batch, d_out, d_ws, ws_bytes, stream):
+    return _check(lib().qsv_expval(h, d_state, int(batch), d_out, d_ws, int(ws_bytes), stream))
+
+
+def qsv_backward(h, d_weights, d_inputs, batch, d_state, d_grad_out, d_ws, ws_bytes,
+                 d_grad_weights, d_grad_inputs, stream):
+    return _check(lib().qsv_backward(h, d_weights, d_inputs, int(batch), d_state, d_grad_out,
+                                     d_ws, int(ws_bytes), d_grad_weights, d_grad_inputs, stream))
+
+
+def qsv_plan_get_info(h):
+    info = qsv_plan_info()
+    _check(lib().qsv_plan_get_info(h, ctypes.byref(info)))
+    return {n: getattr(info, n) for n, _ in qsv_plan_info._fields_}
+
+
+def qsv_plan_gate_order(h, which, n_gates):
+    out = np.zeros(max(n_gates, 1), dtype=np.int32)
+    _check(lib().qsv_plan_gate_order(h, int(which), out.ctypes.data))
+    return out[:n_gates]
+
+
+def qsv_plan_gate_blocks(h, n_gates):
+    out = np.zeros(max(n_gates, 1), dtype=np.int32)
+    _check(lib().qsv_plan_gate_blocks(h, out.ctypes.data))
+    return out[:n_gates]
+
+
+def qsv_strerror(code):
+    return lib().qsv_strerror(int(code)).decode()
+
+
+def qsv_last_error():
+    return lib().qsv_last_error().decode()
+
+
+# -- plan owner with torch-allocated workspaces -------------------------------------
+
+def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
+              max_pass_grads=None):
+    o = qsv_default_opts()
+    o.method = METHOD[method] if isinstance(method, str) else int(method)
+    if fuse_width is not None:
+        o.fuse_width = fuse_width
+    if tile_qubits is not None:
+        o.tile_qubits = tile_qubits
+    if low_qubits is not None:
+        o.low_qubits = low_qubits
+    if max_pass_grads is not None:
+        o.max_pass_grads = max_pass_grads
+    return o
+
+
+class Plan:
+    """Owns a qsv plan; calls run on torch's current HIP stream."""
+
+    def __init__(self, n_qubits, gates, n_weights, n_inputs, **opts):
+        self.n_qubits = int(n_qubits)
+        self.n_gates = len(gates)
+        self.n_weights = int(n_weights)
+        self.n_inputs = int(n_inputs)
+        self.opts = make_opts(**opts)
+        self.handle = qsv_plan(n_qubits, gates, n_weights, n_inputs, self.opts)
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            qsv_plan_destroy(h)
+            self.handle = None
+
+    def info(self):
+        return qsv_plan_get_info(self.handle)
+
+    def gate_order(self, which):
+        return qsv_plan_gate_order(self.handle, which, self.n_gates)
+
+    def gate_blocks(self):
+        return qsv_plan_gate_blocks(self.handle, self.n_gates)
+
+    def workspace(self, batch, op, device):
+        import torch
+        n = qsv_workspace_size(self.handle, batch, op)
+        key = (op, str(device))
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+    @staticmethod
+    def _ptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    @staticmethod
+    def _stream(device):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+    def forward(self, weights, inputs, batch, state=None):
+        """weights (P,) f32, inputs (B, n_inputs) f32 on the GPU -> state (B, 2^W) complex64."""
+        import torch
+        dev = weights.device if weights is not None and weights.numel() else inputs.device
+        if state is None:
+            state = torch.empty((batch, 1 << self.n_qubits), dtype=torch.complex64, device=dev)
+        ws = self.workspace(batch, OP_FORWARD, dev)
+        qsv_forward(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
+                    self._ptr(state), self._ptr(ws), ws.numel(), self._stream(dev))
+        return state
+
+    def expval(self, state, out=None):
+        import torch
+        batch = state.shape[0]
+        if out is None:
+            out = torch.empty((batch, self.n_qubits), dtype=torch.float64, device=state.device)
+        ws = self.workspace(batch, OP_EXPVAL, state.device)
+        qsv_expval(self.handle, self._ptr(state), batch, self._ptr(out), self._ptr(ws), ws.numel(),
+                   self._stream(state.device))
+        return out
+
+    def backward(self, weights, inputs, state, grad_out, want_inputs=True, gw=None, gx=None):
+        import torch
+        batch = state.shape[0]
+        dev = state.device
+        if gw is None:
+            gw = torch.empty((max(self.n_weights, 1),), dtype=torch.float64, device=dev)
+        if gx is None and want_inputs and self.n_inputs:
+            gx = torch.empty((batch, self.n_inputs), dtype=torch.float64, device=dev)
+        ws = self.workspace(batch, OP_BACKWARD, dev)
+        go = grad_out.to(torch.float64).contiguous()
+        qsv_backward(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
+                     self._ptr(state), self._ptr(go), self._ptr(ws), ws.numel(), self._ptr(gw),
+                     self._ptr(gx) if want_inputs else None, self._stream(dev))
+        return gw[: self.n_weights], gx
+
+
+def _f32(t):
+    if t is None or t.numel() == 0:
+        return None
+    import torch
+    assert t.dtype == torch.float32 and t.is_contiguous(), "angles must be contiguous float32"
+    return t

@@ -1,0 +1,179 @@
+// plan.hpp -- host-side plan: gate-matrix cache, split, pass/stage schedule,
+// and the flat tables the kernels read. Shared by planner.cpp and qsv.hip.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qsv.h"
+
+namespace qsv {
+
+constexpr int kRegBits = 4;            // amplitudes per thread in a tile = 2^kRegBits
+constexpr int kRegs = 1 << kRegBits;
+constexpr int kMaxTileQubits = 12;
+constexpr int kMaxQ = 32;
+
+// ---- device-visible tables (plain old data, copied verbatim to the GPU) ----
+
+// One gate of the cache: its matrix is C + cos(theta/2) A + sin(theta/2) S
+// (2x2 complex, row-major, interleaved re/im), the generalisation of Eq. (1)
+// to every kind. Fixed gates have A = S = 0.
+struct DGate {
+    int32_t kind, src, idx, pad;
+    double C[8], A[8], S[8];
+};
+
+// A recipe: the ordered product of `count` gates (recipe_gates[first ..]),
+// optionally daggered. Evaluated once per call (per sample if any gate reads
+// an input). out >= 0: shared slot; out < 0: per-sample slot (-out - 1).
+struct DRecipe {
+    int32_t first, count, dagger, out;
+};
+
+enum OpKind : int32_t {
+    OP_U2 = 0,     // generic 2x2 on register position `pos`, optional control
+    OP_REAL = 1,   // 2x2 with real entries
+    OP_RXL = 2,    // [[a, ib], [ib, a]] with real a, b (RX family)
+    OP_DIAG = 3,   // diag(m00, m11) on a qubit; pos >= 0 register, else `sh` global shift
+    OP_SIGN = 4,   // product of CZ / Z signs (a sign group), see DTerm
+    OP_SWAP = 5,   // X / CNOT target: exchange the pair (optional control)
+    OP_GX = 6,     // gradient partial, generator X on `pos` (optional control)
+    OP_GY = 7,     // gradient partial, generator Y on `pos`
+    OP_GZ = 8,     // gradient partial, generator Z; pos >= 0 register, else `sh`
+};
+
+// Control encoding: ctl = -1 none; 0..3 register position; 0x100 | shift for
+// a qubit outside the registers (thread bit or out-of-tile bit).
+constexpr int32_t kCtlNonReg = 0x100;
+
+struct DOp {
+    int32_t kind;
+    int32_t pos;      // register position of the target, or -1
+    int32_t ctl;      // control, see above
+    int32_t mat;      // matrix slot (>= 0 shared, < 0 per-sample: -mat-1)
+    int32_t slot;     // local gradient slot within the pass (OP_G*)
+    int32_t sh;       // global bit shift for non-register diagonal / GZ ops
+    int32_t term0;    // OP_SIGN: first term
+    int32_t nterm;    // OP_SIGN: number of terms; uniform 16-bit mask in `pos`
+};
+
+// Sign term of an OP_SIGN group, for one stage layout:
+//  s1 <  0: if bit s0 of the thread's global index is set, flip `mask` registers;
+//  s1 >= 0: if bits s0 and s1 are both set, flip all registers.
+struct DTerm {
+    int32_t s0, s1, mask, pad;
+};
+
+struct DStage {
+    int32_t reg[kRegBits];  // local tile bits held in registers, position p -> local bit
+    int32_t op0, op1;       // ops [op0, op1)
+    int32_t pad[2];
+};
+
+enum PassFlags : int32_t {
+    PF_FIRST_BWD = 1,  // backward: read psi_N from the caller's state, build lambda on the fly
+    PF_LAST_BWD = 2,   // backward: nothing is written back
+    PF_INIT_FWD = 4,   // forward: generate the product-state init instead of loading
+};
+
+struct DPass {
+    int32_t m;            // tile qubits
+    int32_t n_stages;
+    int32_t stage0;
+    int32_t flags;
+    int32_t n_gslots;     // gradient slots used by this pass
+    int32_t gslot0;       // first entry in gslot_map
+    int32_t pad[2];
+    int32_t lq[kMaxQ];    // local tile bit j -> global bit shift (W-1-qubit), j < m
+    int32_t oq[kMaxQ];    // tile-index bit k -> global bit shift, k < W-m
+};
+
+// Per-gate (plain method) launch description.
+struct PGate {
+    int32_t gate;       // gate index
+    int32_t cls;        // OpKind of the apply step (U2/REAL/RXL/DIAG/SIGN/SWAP)
+    int32_t tsh, csh;   // target / control global shifts (-1 none)
+    int32_t mat;        // matrix slot
+    int32_t grad;       // OP_GX/GY/GZ or -1
+    int32_t slot;       // parametric gate ordinal or -1
+    int32_t sh2;        // CZ second shift
+};
+
+// ---- host plan ----
+
+struct Block {
+    std::vector<int> gates;
+    uint32_t Q = 0;   // all qubits touched
+};
+
+struct DeviceTables {
+    void* base = nullptr;  // one allocation holding everything below
+    DGate* gates = nullptr;
+    DRecipe* recipes = nullptr;
+    int32_t* recipe_gates = nullptr;
+    DPass* fwd_pass = nullptr;
+    DPass* bwd_pass = nullptr;
+    DStage* stages = nullptr;
+    DOp* ops = nullptr;
+    DTerm* terms = nullptr;
+    int32_t* gslot_map = nullptr;
+    int32_t* prefix_mat = nullptr;
+    int32_t* grad_csr = nullptr;   // weights then inputs: offsets, then slot lists
+};
+
+}  // namespace qsv
+
+struct qsv_plan_s {
+    uint32_t magic;
+    int W, n_gates, n_weights, n_inputs;
+    qsv_opts opts;
+    std::vector<qsv_gate> gates;
+
+    // gate-matrix cache
+    std::vector<qsv::DGate> dgates;
+    std::vector<qsv::DRecipe> recipes;
+    std::vector<int32_t> recipe_gates;
+    int n_shared_mats = 0, n_ps_mats = 0;
+
+    // product-state prefix: per qubit a matrix slot (identity recipe if none)
+    std::vector<int> prefix_gates;      // gate indices folded into init
+    std::vector<int32_t> prefix_mat;    // W entries
+
+    // splitter output over the whole gate list
+    std::vector<qsv::Block> blocks;
+    std::vector<int32_t> block_of_gate;
+
+    // fused schedule
+    std::vector<qsv::DPass> fwd_pass, bwd_pass;
+    std::vector<qsv::DStage> stages;
+    std::vector<qsv::DOp> ops;
+    std::vector<qsv::DTerm> terms;
+    std::vector<int32_t> gslot_map;     // local gradient slot -> parametric ordinal
+
+    // per-gate schedule
+    std::vector<qsv::PGate> pg_fwd, pg_bwd;
+
+    // parametric gates and gradient gathering
+    std::vector<int32_t> param_ordinal;  // gate -> ordinal or -1
+    std::vector<int32_t> param_gate;     // ordinal -> gate
+    std::vector<int32_t> grad_csr;       // [n_weights+1 offsets][n_inputs+1 offsets][slots...]
+    int n_param = 0;
+
+    // gate orders for introspection
+    std::vector<int32_t> fwd_order, bwd_order;
+    int n_fwd_stages = 0, n_bwd_stages = 0;
+
+    // lazily created device copies, per device ordinal
+    mutable std::mutex dev_mu;
+    mutable std::map<int, qsv::DeviceTables> dev;
+};
+
+namespace qsv {
+constexpr uint32_t kPlanMagic = 0x51535650u;  // "QSVP"
+int build_plan(qsv_plan_t* p);                  // planner.cpp
+void set_error(const std::string& msg);       // api
+}  // namespace qsv

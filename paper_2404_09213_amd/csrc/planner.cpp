@@ -1,0 +1,556 @@
+// planner.cpp -- host-only plan construction (no device calls).
+//
+// 1. Gate-matrix cache (section "Gate Matrix Caching", Eq. (1)): every gate is
+//    stored as constant partial matrices C, A, S with matrix(theta) =
+//    C + cos(theta/2) A + sin(theta/2) S. Nothing is Kronecker-expanded: the
+//    kernels apply 2x2 blocks by index arithmetic instead of Eq. (2)'s
+//    2^W x 2^W operators.
+// 2. Product-state prefix: the 1-qubit gates that precede every multi-qubit
+//    gate on their qubit act on |0...0> qubit by qubit, so the forward starts
+//    from their tensor product (this covers the angle-embedding layer).
+// 3. Splitter (section "Circuit Splitting"): gates are placed greedily, in
+//    program order, into blocks of at most k qubits; a gate goes into the
+//    first block at or after the last block touching one of its qubits that
+//    still has room, else into a new block.
+// 4. Pass builder: blocks are packed into passes; a pass is one read and one
+//    write of the state in tiles of 2^m amplitudes whose qubits cover every
+//    qubit the pass acts on non-diagonally, plus the c lowest-stride qubits.
+//    A block may move ahead of blocks it commutes with.
+// 5. Stage builder: inside a pass, each thread keeps 2^4 amplitudes spanning 4
+//    tile qubits in registers; ops are grouped into stages whose non-diagonal
+//    qubits fit those 4 register bits; between stages the tile is re-laid out
+//    through LDS.
+//
+// Commutation rule used by 4 and 5: a gate acts "densely" on the qubits where
+// it is not block-diagonal in the computational basis (1-qubit non-diagonal
+// gates, targets of CNOT/CRX) and "diagonally" on the others (RZ, Z, CZ and
+// controls). Two gates commute when neither acts densely on a qubit the
+// other touches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "plan.hpp"
+
+namespace qsv {
+namespace {
+
+inline int popc(uint32_t x) { return __builtin_popcount(x); }
+
+bool is_two(int k) { return k == QSV_CNOT || k == QSV_CZ || k == QSV_CRX; }
+bool is_param_kind(int k) { return k == QSV_RX || k == QSV_RY || k == QSV_RZ || k == QSV_CRX; }
+
+uint32_t qmask(const qsv_gate& g) {
+    return (1u << g.q0) | (is_two(g.kind) ? (1u << g.q1) : 0u);
+}
+
+// Dense (D) and diagonal/control (C) qubit masks of a gate.
+void gate_sets(const qsv_gate& g, uint32_t& D, uint32_t& C) {
+    switch (g.kind) {
+    case QSV_Z: case QSV_RZ: D = 0; C = 1u << g.q0; break;
+    case QSV_CZ: D = 0; C = (1u << g.q0) | (1u << g.q1); break;
+    case QSV_CNOT: case QSV_CRX: D = 1u << g.q1; C = 1u << g.q0; break;
+    default: D = 1u << g.q0; C = 0; break;
+    }
+}
+
+bool conflicts(uint32_t D1, uint32_t C1, uint32_t D2, uint32_t C2) {
+    return (D1 & (D2 | C2)) || (D2 & (D1 | C1));
+}
+
+void setm(double* M, int r, int c, double re, double im) {
+    M[(r * 2 + c) * 2] = re;
+    M[(r * 2 + c) * 2 + 1] = im;
+}
+
+void fill_partials(DGate& d, const qsv_gate& g) {
+    std::memset(&d, 0, sizeof d);
+    d.kind = g.kind;
+    d.src = g.src;
+    d.idx = g.idx;
+    const double r = 1.0 / std::sqrt(2.0);
+    switch (g.kind) {
+    case QSV_H: setm(d.C, 0, 0, r, 0); setm(d.C, 0, 1, r, 0); setm(d.C, 1, 0, r, 0); setm(d.C, 1, 1, -r, 0); break;
+    case QSV_X: case QSV_CNOT: setm(d.C, 0, 1, 1, 0); setm(d.C, 1, 0, 1, 0); break;
+    case QSV_Y: setm(d.C, 0, 1, 0, -1); setm(d.C, 1, 0, 0, 1); break;
+    case QSV_Z: case QSV_CZ: setm(d.C, 0, 0, 1, 0); setm(d.C, 1, 1, -1, 0); break;
+    case QSV_RX: case QSV_CRX:  // cos I + sin (-i X)
+        setm(d.A, 0, 0, 1, 0); setm(d.A, 1, 1, 1, 0);
+        setm(d.S, 0, 1, 0, -1); setm(d.S, 1, 0, 0, -1); break;
+    case QSV_RY:  // cos I + sin [[0,-1],[1,0]]
+        setm(d.A, 0, 0, 1, 0); setm(d.A, 1, 1, 1, 0);
+        setm(d.S, 0, 1, -1, 0); setm(d.S, 1, 0, 1, 0); break;
+    case QSV_RZ:  // cos I + sin (-i Z)
+        setm(d.A, 0, 0, 1, 0); setm(d.A, 1, 1, 1, 0);
+        setm(d.S, 0, 0, 0, -1); setm(d.S, 1, 1, 0, 1); break;
+    }
+}
+
+// Structural class of a product of gates (for the kernels' cheaper variants).
+int recipe_class(const qsv_plan_t* p, const std::vector<int>& gs) {
+    bool all_diag = true, all_real = true;
+    for (int g : gs) {
+        const int k = p->gates[g].kind;
+        if (!(k == QSV_Z || k == QSV_RZ || k == QSV_CZ)) all_diag = false;
+        if (!(k == QSV_H || k == QSV_X || k == QSV_Z || k == QSV_RY || k == QSV_CNOT || k == QSV_CZ))
+            all_real = false;
+    }
+    if (all_diag) return OP_DIAG;
+    if (gs.size() == 1) {
+        const int k = p->gates[gs[0]].kind;
+        if (k == QSV_X || k == QSV_CNOT) return OP_SWAP;
+        if (k == QSV_RX || k == QSV_CRX) return OP_RXL;
+    }
+    return all_real ? OP_REAL : OP_U2;
+}
+
+int add_recipe(qsv_plan_t* p, const std::vector<int>& gs, bool dagger) {
+    DRecipe r;
+    r.first = (int32_t)p->recipe_gates.size();
+    r.count = (int32_t)gs.size();
+    r.dagger = dagger ? 1 : 0;
+    bool per_sample = false;
+    for (int g : gs) {
+        p->recipe_gates.push_back(g);
+        if (p->gates[g].src == QSV_SRC_INPUT) per_sample = true;
+    }
+    r.out = per_sample ? -(p->n_ps_mats++) - 1 : p->n_shared_mats++;
+    p->recipes.push_back(r);
+    return r.out;
+}
+
+std::vector<Block> split(const qsv_plan_t* p, const std::vector<int>& seq, int k) {
+    std::vector<Block> blocks;
+    std::vector<int> last(p->W, -1);
+    for (int g : seq) {
+        const uint32_t q = qmask(p->gates[g]);
+        int jstar = -1;
+        for (int b = 0; b < p->W; ++b)
+            if (q >> b & 1) jstar = std::max(jstar, last[b]);
+        int placed = -1;
+        for (int j = std::max(jstar, 0); j < (int)blocks.size(); ++j)
+            if (popc(blocks[j].Q | q) <= k) { placed = j; break; }
+        if (placed < 0) { blocks.emplace_back(); placed = (int)blocks.size() - 1; }
+        blocks[placed].gates.push_back(g);
+        blocks[placed].Q |= q;
+        for (int b = 0; b < p->W; ++b)
+            if (q >> b & 1) last[b] = placed;
+    }
+    return blocks;
+}
+
+struct BlockSets { uint32_t D = 0, C = 0; int nparam = 0; };
+
+BlockSets block_sets(const qsv_plan_t* p, const Block& b) {
+    BlockSets s;
+    for (int g : b.gates) {
+        uint32_t D, C;
+        gate_sets(p->gates[g], D, C);
+        s.D |= D;
+        s.C |= C;
+        if (p->gates[g].src != QSV_SRC_NONE) s.nparam++;
+    }
+    s.C &= ~s.D;
+    return s;
+}
+
+uint32_t low_mask(int W, int c) {
+    uint32_t m = 0;
+    for (int i = 0; i < c; ++i) m |= 1u << (W - 1 - i);  // qubit W-1 has stride 1
+    return m;
+}
+
+// Pack blocks into passes; returns per pass the gate list in execution order.
+std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block> blocks, int m,
+                                          int c, int max_grads, std::vector<uint32_t>& pass_dense) {
+    std::vector<std::vector<int>> passes;
+    const uint32_t low = low_mask(p->W, c);
+    std::vector<Block> remaining = std::move(blocks);
+    while (!remaining.empty()) {
+        uint32_t T = 0, sD = 0, sC = 0;
+        int ngrad = 0;
+        std::vector<int> gates;
+        std::vector<Block> skipped;
+        bool any = false;
+        for (auto& b : remaining) {
+            BlockSets s = block_sets(p, b);
+            const bool conflict = conflicts(s.D, s.C, sD, sC);
+            if (!conflict && popc(T | s.D | low) <= m && ngrad + s.nparam <= max_grads) {
+                T |= s.D;
+                ngrad += s.nparam;
+                gates.insert(gates.end(), b.gates.begin(), b.gates.end());
+                any = true;
+            } else {
+                skipped.push_back(b);
+                sD |= s.D;
+                sC |= s.C;
+            }
+        }
+        if (!any) {
+            // The first block alone does not fit a tile: split it into single gates.
+            Block big = remaining.front();
+            std::vector<Block> singles;
+            for (int g : big.gates) {
+                Block one;
+                one.gates.push_back(g);
+                one.Q = qmask(p->gates[g]);
+                singles.push_back(one);
+            }
+            remaining.erase(remaining.begin());
+            remaining.insert(remaining.begin(), singles.begin(), singles.end());
+            continue;
+        }
+        passes.push_back(gates);
+        pass_dense.push_back(T);
+        remaining = std::move(skipped);
+    }
+    return passes;
+}
+
+// One schedulable unit inside a pass: a fused 1-qubit chain or a 2-qubit gate.
+struct Unit {
+    std::vector<int> gates;  // in application order
+    uint32_t D = 0, C = 0;
+    int qubit = -1;          // chain qubit, or target of a 2-qubit gate
+};
+
+std::vector<Unit> fwd_units(const qsv_plan_t* p, const std::vector<int>& gates) {
+    std::vector<Unit> units;
+    std::vector<int> open(p->W, -1);
+    for (int g : gates) {
+        const qsv_gate& G = p->gates[g];
+        if (!is_two(G.kind)) {
+            int& u = open[G.q0];
+            if (u < 0) {
+                units.emplace_back();
+                u = (int)units.size() - 1;
+                units[u].qubit = G.q0;
+            }
+            units[u].gates.push_back(g);
+            uint32_t D, C;
+            gate_sets(G, D, C);
+            units[u].D |= D;
+            units[u].C |= C;
+        } else {
+            open[G.q0] = open[G.q1] = -1;
+            Unit x;
+            x.gates.push_back(g);
+            gate_sets(G, x.D, x.C);
+            x.qubit = G.q1;
+            units.push_back(x);
+        }
+    }
+    for (auto& u : units) u.C &= ~u.D;
+    return units;
+}
+
+std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates) {
+    std::vector<Unit> units;
+    for (auto it = gates.rbegin(); it != gates.rend(); ++it) {
+        Unit x;
+        x.gates.push_back(*it);
+        gate_sets(p->gates[*it], x.D, x.C);
+        const qsv_gate& G = p->gates[*it];
+        x.qubit = is_two(G.kind) ? G.q1 : G.q0;
+        units.push_back(x);
+    }
+    return units;
+}
+
+// Greedy stage grouping: each stage's dense qubits fit the register bits.
+std::vector<std::pair<uint32_t, std::vector<int>>> group_stages(const std::vector<Unit>& units) {
+    std::vector<std::pair<uint32_t, std::vector<int>>> stages;
+    std::vector<int> remaining(units.size());
+    for (size_t i = 0; i < units.size(); ++i) remaining[i] = (int)i;
+    while (!remaining.empty()) {
+        uint32_t R = 0, sD = 0, sC = 0;
+        std::vector<int> taken, skipped;
+        for (int u : remaining) {
+            const Unit& U = units[u];
+            if (!conflicts(U.D, U.C, sD, sC) && popc(R | U.D) <= kRegBits) {
+                R |= U.D;
+                taken.push_back(u);
+            } else {
+                skipped.push_back(u);
+                sD |= U.D;
+                sC |= U.C;
+            }
+        }
+        stages.emplace_back(R, taken);
+        remaining = skipped;
+    }
+    return stages;
+}
+
+// Builds one DPass (tile qubits + stages + ops) from a pass's gate list.
+struct PassBuilder {
+    qsv_plan_t* p;
+    bool backward;
+
+    void build(const std::vector<int>& gates, uint32_t dense, int m, int c, int flags,
+               std::vector<DPass>& out, std::vector<int32_t>& order) {
+        const int W = p->W;
+        DPass ps;
+        std::memset(&ps, 0, sizeof ps);
+        ps.m = m;
+        ps.flags = flags;
+        // tile qubits: dense set + c lowest + fill with the lowest remaining
+        uint32_t tile = dense | low_mask(W, c);
+        for (int q = W - 1; q >= 0 && popc(tile) < m; --q) tile |= 1u << q;
+        // local bits ordered by ascending global shift (qubit W-1 first)
+        int local_of_qubit[kMaxQ];
+        int j = 0, k = 0;
+        for (int q = W - 1; q >= 0; --q) {
+            if (tile >> q & 1) { local_of_qubit[q] = j; ps.lq[j++] = W - 1 - q; }
+            else { local_of_qubit[q] = -1; ps.oq[k++] = W - 1 - q; }
+        }
+        std::vector<Unit> units = backward ? bwd_units(p, gates) : fwd_units(p, gates);
+        auto groups = group_stages(units);
+        ps.stage0 = (int32_t)p->stages.size();
+        ps.n_stages = (int32_t)groups.size();
+        ps.gslot0 = (int32_t)p->gslot_map.size();
+        int nslot = 0;
+        for (auto& grp : groups) {
+            DStage st;
+            std::memset(&st, 0, sizeof st);
+            // register bits: the stage's dense qubits, padded with the top local bits
+            std::vector<int> regs;
+            for (int q = 0; q < W; ++q)
+                if (grp.first >> q & 1) regs.push_back(local_of_qubit[q]);
+            for (int lb = m - 1; lb >= 0 && (int)regs.size() < kRegBits; --lb)
+                if (std::find(regs.begin(), regs.end(), lb) == regs.end()) regs.push_back(lb);
+            std::sort(regs.begin(), regs.end());
+            for (int i = 0; i < kRegBits; ++i) st.reg[i] = regs[i];
+            auto pos_of = [&](int qubit) -> int {
+                const int lb = local_of_qubit[qubit];
+                for (int i = 0; i < kRegBits; ++i)
+                    if (lb >= 0 && st.reg[i] == lb) return i;
+                return -1;
+            };
+            st.op0 = (int32_t)p->ops.size();
+            int sign_op = -1;  // open OP_SIGN being extended
+            for (int ui : grp.second) {
+                const Unit& U = units[ui];
+                for (int g : U.gates) order.push_back(g);
+                const qsv_gate& G = p->gates[U.gates[0]];
+                const bool is_cz = U.gates.size() == 1 && G.kind == QSV_CZ;
+                if (is_cz) {
+                    if (sign_op < 0) {
+                        DOp o;
+                        std::memset(&o, 0, sizeof o);
+                        o.kind = OP_SIGN;
+                        o.pos = 0;  // uniform mask
+                        o.ctl = -1;
+                        o.term0 = (int32_t)p->terms.size();
+                        o.nterm = 0;
+                        p->ops.push_back(o);
+                        sign_op = (int)p->ops.size() - 1;
+                    }
+                    DOp& o = p->ops[sign_op];
+                    const int pa = pos_of(G.q0), pb = pos_of(G.q1);
+                    const int sa = W - 1 - G.q0, sb = W - 1 - G.q1;
+                    if (pa >= 0 && pb >= 0) {
+                        int mask = 0;
+                        for (int r = 0; r < kRegs; ++r)
+                            if ((r >> pa & 1) && (r >> pb & 1)) mask |= 1 << r;
+                        o.pos ^= mask;
+                    } else {
+                        DTerm t;
+                        std::memset(&t, 0, sizeof t);
+                        if (pa >= 0 || pb >= 0) {
+                            const int pr = pa >= 0 ? pa : pb;
+                            t.s0 = pa >= 0 ? sb : sa;
+                            t.s1 = -1;
+                            for (int r = 0; r < kRegs; ++r)
+                                if (r >> pr & 1) t.mask |= 1 << r;
+                        } else {
+                            t.s0 = sa;
+                            t.s1 = sb;
+                            t.mask = 0xFFFF;
+                        }
+                        p->terms.push_back(t);
+                        o.nterm++;
+                    }
+                    continue;
+                }
+                sign_op = -1;
+                if (backward) {
+                    // gradient partial (before uncomputing the gate), then U^dagger
+                    const int g = U.gates[0];
+                    if (G.src != QSV_SRC_NONE) {
+                        DOp o;
+                        std::memset(&o, 0, sizeof o);
+                        o.kind = G.kind == QSV_RY ? OP_GY : G.kind == QSV_RZ ? OP_GZ : OP_GX;
+                        o.pos = pos_of(U.qubit);
+                        o.sh = W - 1 - U.qubit;
+                        o.ctl = -1;
+                        if (G.kind == QSV_CRX) {
+                            const int pc = pos_of(G.q0);
+                            o.ctl = pc >= 0 ? pc : (kCtlNonReg | (W - 1 - G.q0));
+                        }
+                        o.mat = 0;
+                        o.slot = nslot++;
+                        p->gslot_map.push_back(p->param_ordinal[g]);
+                        p->ops.push_back(o);
+                    }
+                }
+                DOp o;
+                std::memset(&o, 0, sizeof o);
+                o.kind = recipe_class(p, U.gates);
+                o.mat = add_recipe(p, U.gates, backward);
+                o.pos = pos_of(U.qubit);
+                o.sh = W - 1 - U.qubit;
+                o.ctl = -1;
+                o.slot = -1;
+                if (is_two(G.kind) && U.gates.size() == 1) {
+                    const int pc = pos_of(G.q0);
+                    o.ctl = pc >= 0 ? pc : (kCtlNonReg | (W - 1 - G.q0));
+                }
+                p->ops.push_back(o);
+            }
+            st.op1 = (int32_t)p->ops.size();
+            p->stages.push_back(st);
+        }
+        ps.n_gslots = nslot;
+        out.push_back(ps);
+    }
+};
+
+int pg_class(const qsv_plan_t* p, int g) {
+    const int k = p->gates[g].kind;
+    if (k == QSV_CZ) return OP_SIGN;
+    return recipe_class(p, std::vector<int>{g});
+}
+
+}  // namespace
+
+int build_plan(qsv_plan_t* p) {
+    const int W = p->W;
+    const qsv_opts& o = p->opts;
+    // gate cache
+    p->dgates.resize(p->n_gates);
+    p->param_ordinal.assign(p->n_gates, -1);
+    for (int g = 0; g < p->n_gates; ++g) {
+        fill_partials(p->dgates[g], p->gates[g]);
+        if (p->gates[g].src != QSV_SRC_NONE) {
+            p->param_ordinal[g] = p->n_param++;
+            p->param_gate.push_back(g);
+        }
+    }
+    // gradient gathering lists
+    {
+        std::vector<std::vector<int>> wl(p->n_weights), xl(p->n_inputs);
+        for (int g = 0; g < p->n_gates; ++g) {
+            const qsv_gate& G = p->gates[g];
+            if (G.src == QSV_SRC_WEIGHT) wl[G.idx].push_back(p->param_ordinal[g]);
+            if (G.src == QSV_SRC_INPUT) xl[G.idx].push_back(p->param_ordinal[g]);
+        }
+        const int head = p->n_weights + 1 + p->n_inputs + 1;
+        p->grad_csr.assign(head, 0);
+        int at = head;
+        for (int j = 0; j < p->n_weights; ++j) { p->grad_csr[j] = at; at += (int)wl[j].size(); }
+        p->grad_csr[p->n_weights] = at;
+        for (int j = 0; j < p->n_inputs; ++j) { p->grad_csr[p->n_weights + 1 + j] = at; at += (int)xl[j].size(); }
+        p->grad_csr[p->n_weights + 1 + p->n_inputs] = at;
+        for (auto& l : wl) p->grad_csr.insert(p->grad_csr.end(), l.begin(), l.end());
+        for (auto& l : xl) p->grad_csr.insert(p->grad_csr.end(), l.begin(), l.end());
+    }
+    // product-state prefix
+    std::vector<int> first2(W, p->n_gates);
+    for (int g = p->n_gates - 1; g >= 0; --g) {
+        const qsv_gate& G = p->gates[g];
+        if (is_two(G.kind)) first2[G.q0] = first2[G.q1] = g;
+    }
+    std::vector<char> in_prefix(p->n_gates, 0);
+    std::vector<std::vector<int>> pre(W);
+    for (int g = 0; g < p->n_gates; ++g) {
+        const qsv_gate& G = p->gates[g];
+        if (!is_two(G.kind) && g < first2[G.q0]) {
+            in_prefix[g] = 1;
+            pre[G.q0].push_back(g);
+            p->prefix_gates.push_back(g);
+        }
+    }
+    p->prefix_mat.resize(W);
+    for (int q = 0; q < W; ++q) p->prefix_mat[q] = add_recipe(p, pre[q], false);
+    std::vector<int> body, all;
+    for (int g = 0; g < p->n_gates; ++g) {
+        all.push_back(g);
+        if (!in_prefix[g]) body.push_back(g);
+    }
+    p->fwd_order = p->prefix_gates;
+
+    // splitter over the whole list (reported; drives the backward schedule)
+    p->blocks = split(p, all, o.fuse_width);
+    p->block_of_gate.assign(p->n_gates, -1);
+    for (size_t b = 0; b < p->blocks.size(); ++b)
+        for (int g : p->blocks[b].gates) p->block_of_gate[g] = (int32_t)b;
+
+    if (o.method == QSV_METHOD_PER_GATE) {
+        for (int g : body) {
+            PGate x;
+            std::memset(&x, 0, sizeof x);
+            const qsv_gate& G = p->gates[g];
+            x.gate = g;
+            x.cls = pg_class(p, g);
+            x.tsh = W - 1 - (is_two(G.kind) ? G.q1 : G.q0);
+            x.csh = (G.kind == QSV_CNOT || G.kind == QSV_CRX) ? W - 1 - G.q0 : -1;
+            x.sh2 = G.kind == QSV_CZ ? W - 1 - G.q0 : -1;
+            x.mat = x.cls == OP_SIGN ? 0 : add_recipe(p, {g}, false);
+            x.grad = -1;
+            x.slot = -1;
+            p->pg_fwd.push_back(x);
+            p->fwd_order.push_back(g);
+        }
+        for (int g = p->n_gates - 1; g >= 0; --g) {
+            PGate x;
+            std::memset(&x, 0, sizeof x);
+            const qsv_gate& G = p->gates[g];
+            x.gate = g;
+            x.cls = pg_class(p, g);
+            x.tsh = W - 1 - (is_two(G.kind) ? G.q1 : G.q0);
+            x.csh = (G.kind == QSV_CNOT || G.kind == QSV_CRX) ? W - 1 - G.q0 : -1;
+            x.sh2 = G.kind == QSV_CZ ? W - 1 - G.q0 : -1;
+            x.mat = x.cls == OP_SIGN ? 0 : add_recipe(p, {g}, true);
+            x.slot = p->param_ordinal[g];
+            x.grad = G.src == QSV_SRC_NONE ? -1
+                   : G.kind == QSV_RY ? OP_GY : G.kind == QSV_RZ ? OP_GZ : OP_GX;
+            p->pg_bwd.push_back(x);
+            p->bwd_order.push_back(g);
+        }
+        return QSV_OK;
+    }
+
+    // fused schedule
+    const int m = std::min(o.tile_qubits, W);
+    const int c = std::min(o.low_qubits, m - 1);
+    // LDS budget for per-wave gradient partials: (threads / 64) x grads x 8 bytes
+    const int threads = std::max(64, 1 << (m - kRegBits));
+    const int exch = (1 << m) * 8;
+    int max_grads = std::min(o.max_pass_grads, (160 * 1024 - exch) / ((threads / 64) * 8));
+    max_grads = std::max(max_grads, 1);
+    {
+        std::vector<uint32_t> dense;
+        auto passes = pack_passes(p, split(p, body, o.fuse_width), m, c, 1 << 30, dense);
+        PassBuilder pb{p, false};
+        for (size_t i = 0; i < passes.size(); ++i)
+            pb.build(passes[i], dense[i], m, c, 0, p->fwd_pass, p->fwd_order);
+    }
+    {
+        std::vector<uint32_t> dense;
+        auto passes = pack_passes(p, p->blocks, m, c, max_grads, dense);
+        PassBuilder pb{p, true};
+        const int n = (int)passes.size();
+        for (int i = n - 1; i >= 0; --i) {
+            int flags = 0;
+            if (i == n - 1) flags |= PF_FIRST_BWD;
+            if (i == 0) flags |= PF_LAST_BWD;
+            pb.build(passes[i], dense[i], m, c, flags, p->bwd_pass, p->bwd_order);
+        }
+    }
+    for (auto& ps : p->fwd_pass) p->n_fwd_stages += ps.n_stages;
+    for (auto& ps : p->bwd_pass) p->n_bwd_stages += ps.n_stages;
+    return QSV_OK;
+}
+
+}  // namespace qsv

@@ -1,0 +1,1333 @@
+// qsv.hip -- gfx950 kernels and the C ABI of libqsv.
+//
+// Kernels (all float32 amplitude arithmetic, float64 reductions):
+//   k_coef          gate-matrix cache evaluation: C + cos(t/2) A + sin(t/2) S per
+//                   gate (Eq. (1) generalised), products of fused chains, daggers
+//   k_init          product-state init from the leading 1-qubit gates (embedding)
+//   k_pg_apply      plain method: one strided sweep of the state per gate
+//   k_pg_adj        plain method, backward: gradient partial + uncompute psi, lambda
+//   k_adj_init      plain method: lambda = (sum_i g_i Z_i) psi_N
+//   k_pass_fwd      fused pass: tile of 2^m amplitudes, register stages, LDS re-layout
+//   k_pass_bwd      fused pass, backward: same tiles for psi and lambda + gradients
+//   k_expval_part / k_expval_final   <Z_i> readout, two deterministic stages
+//   k_grad_reduce   gradient partials -> weight (batch-summed) and input gradients
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "plan.hpp"
+
+using namespace qsv;
+
+// ----------------------------------------------------------------------------
+// error state
+// ----------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+namespace qsv {
+void set_error(const std::string& msg) { g_last_error = msg; }
+}
+
+#define HIP_TRY(expr)                                                            \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));        \
+            return QSV_ERR_HIP;                                                  \
+        }                                                                        \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// device helpers
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+struct M2 { float2 m00, m01, m10, m11; };
+
+__device__ __forceinline__ const float* mat_ptr(const float* mats, int32_t slot, int b,
+                                                int n_shared, int n_ps) {
+    return slot >= 0 ? mats + 8 * (size_t)slot
+                     : mats + 8 * ((size_t)n_shared + (size_t)b * n_ps + (size_t)(-slot - 1));
+}
+
+__device__ __forceinline__ M2 load_m2(const float* p) {
+    M2 m;
+    m.m00 = make_float2(p[0], p[1]);
+    m.m01 = make_float2(p[2], p[3]);
+    m.m10 = make_float2(p[4], p[5]);
+    m.m11 = make_float2(p[6], p[7]);
+    return m;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float im_conj_mul(float2 l, float2 p) { return l.x * p.y - l.y * p.x; }
+__device__ __forceinline__ float re_conj_mul(float2 l, float2 p) { return l.x * p.x + l.y * p.y; }
+
+// Bank-conflict swizzle of a tile-local amplitude index (bijection on [0, 2^m)).
+__device__ __forceinline__ int swz(int l) { return l ^ (((l >> 5) ^ (l >> 10)) & 31); }
+
+__device__ __forceinline__ int64_t insert_bit(int64_t x, int s, int v) {
+    const int64_t lo = x & ((int64_t(1) << s) - 1);
+    return ((x >> s) << (s + 1)) | (int64_t(v) << s) | lo;
+}
+
+// ----------------------------------------------------------------------------
+// gate-matrix cache evaluation
+// ----------------------------------------------------------------------------
+__global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restrict__ recipes,
+                       const int32_t* __restrict__ rg, int n_recipes,
+                       const float* __restrict__ weights, const float* __restrict__ inputs,
+                       int n_inputs, int n_shared, int n_ps, float* __restrict__ mats) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (r >= n_recipes) return;
+    const DRecipe R = recipes[r];
+    if (R.out >= 0 && b != 0) return;
+    double M[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+    for (int i = 0; i < R.count; ++i) {
+        const DGate& G = gates[rg[R.first + i]];
+        double th = 0.0;
+        if (G.src == QSV_SRC_WEIGHT) th = (double)weights[G.idx];
+        else if (G.src == QSV_SRC_INPUT) th = (double)inputs[(size_t)b * n_inputs + G.idx];
+        double s, c;
+        sincos(0.5 * th, &s, &c);
+        double g[8];
+        for (int e = 0; e < 8; ++e) g[e] = G.C[e] + c * G.A[e] + s * G.S[e];
+        // M <- g * M (later gates act on the left)
+        double N[8];
+        for (int row = 0; row < 2; ++row)
+            for (int col = 0; col < 2; ++col) {
+                double re = 0, im = 0;
+                for (int k = 0; k < 2; ++k) {
+                    const double ar = g[(row * 2 + k) * 2], ai = g[(row * 2 + k) * 2 + 1];
+                    const double br = M[(k * 2 + col) * 2], bi = M[(k * 2 + col) * 2 + 1];
+                    re += ar * br - ai * bi;
+                    im += ar * bi + ai * br;
+                }
+                N[(row * 2 + col) * 2] = re;
+                N[(row * 2 + col) * 2 + 1] = im;
+            }
+        for (int e = 0; e < 8; ++e) M[e] = N[e];
+    }
+    float out[8];
+    if (R.dagger) {
+        out[0] = (float)M[0]; out[1] = (float)-M[1];  // m00*
+        out[2] = (float)M[4]; out[3] = (float)-M[5];  // m10*
+        out[4] = (float)M[2]; out[5] = (float)-M[3];  // m01*
+        out[6] = (float)M[6]; out[7] = (float)-M[7];  // m11*
+    } else {
+        for (int e = 0; e < 8; ++e) out[e] = (float)M[e];
+    }
+    float* dst = R.out >= 0 ? mats + 8 * (size_t)R.out
+                            : mats + 8 * ((size_t)n_shared + (size_t)b * n_ps + (size_t)(-R.out - 1));
+    for (int e = 0; e < 8; ++e) dst[e] = out[e];
+}
+
+// ----------------------------------------------------------------------------
+// product-state init: amp(idx) = prod_q v_q[bit_q(idx)], v_q = column 0 of the
+// prefix matrix of qubit q. Work split: chunk of 2^cb amplitudes per block,
+// lanes over the low tb bits, a loop over the next jb bits.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float2 prefix_v(const float* mats, const int32_t* pm, int q, int bit,
+                                           int b, int n_shared, int n_ps) {
+    const float* M = mat_ptr(mats, pm[q], b, n_shared, n_ps);
+    return bit ? make_float2(M[4], M[5]) : make_float2(M[0], M[1]);
+}
+
+__global__ __launch_bounds__(256) void k_init(float2* __restrict__ state, int W,
+                                              const int32_t* __restrict__ pm,
+                                              const float* __restrict__ mats, int n_shared,
+                                              int n_ps) {
+    const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
+    const int t = threadIdx.x;
+    if (t >= (1 << tb)) return;
+    const int b = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    float2 P = make_float2(1.f, 0.f);
+    for (int s = 0; s < tb; ++s) P = cmul(P, prefix_v(mats, pm, W - 1 - s, (t >> s) & 1, b, n_shared, n_ps));
+    for (int s = cb; s < W; ++s)
+        P = cmul(P, prefix_v(mats, pm, W - 1 - s, (int)((chunk >> (s - cb)) & 1), b, n_shared, n_ps));
+    float2* st = state + ((size_t)b << W);
+    for (int j = 0; j < (1 << jb); ++j) {
+        float2 Q = P;
+        for (int s = tb; s < cb; ++s)
+            Q = cmul(Q, prefix_v(mats, pm, W - 1 - s, (j >> (s - tb)) & 1, b, n_shared, n_ps));
+        st[(chunk << cb) | ((int64_t)j << tb) | t] = Q;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// readout
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_expval_part(const float2* __restrict__ state, int W,
+                                                     double* __restrict__ part) {
+    __shared__ double red[4][14];
+    const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
+    const int t = threadIdx.x;
+    const int b = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    const int64_t nchunk = gridDim.x;
+    const float2* st = state + ((size_t)b << W);
+    float T = 0.f, S[4] = {0.f, 0.f, 0.f, 0.f};
+    if (t < (1 << tb)) {
+        for (int j = 0; j < (1 << jb); ++j) {
+            const float2 a = st[(chunk << cb) | ((int64_t)j << tb) | t];
+            const float p = a.x * a.x + a.y * a.y;
+            T += p;
+            for (int i = 0; i < jb; ++i)
+                if ((j >> i) & 1) S[i] += p;
+        }
+    }
+    // values: [0] total, [1..4] j-bit sums, [5..12] thread-bit weighted totals
+    double v[13];
+    v[0] = T;
+    for (int i = 0; i < 4; ++i) v[1 + i] = S[i];
+    for (int s = 0; s < 8; ++s) v[5 + s] = ((t >> s) & 1) ? (double)T : 0.0;
+    const int wave = t >> 6, lane = t & 63;
+    for (int k = 0; k < 13; ++k) {
+        const double r = wave_sum(v[k]);
+        if (lane == 0) red[wave][k] = r;
+    }
+    __syncthreads();
+    if (t < W) {
+        auto tot = [&](int k) { return red[0][k] + red[1][k] + red[2][k] + red[3][k]; };
+        const int s = W - 1 - t;  // qubit t has shift s
+        const double Tsum = tot(0);
+        double e;
+        if (s < tb) e = Tsum - 2.0 * tot(5 + s);
+        else if (s < cb) e = Tsum - 2.0 * tot(1 + (s - tb));
+        else e = ((chunk >> (s - cb)) & 1) ? -Tsum : Tsum;
+        part[((size_t)b * nchunk + chunk) * W + t] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_expval_final(const double* __restrict__ part, int W,
+                                                      int64_t nchunk, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int b = blockIdx.y, i = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t c = t; c < nchunk; c += 256) s += part[((size_t)b * nchunk + c) * W + i];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[(size_t)b * W + i] = red[0];
+}
+
+// ----------------------------------------------------------------------------
+// gradient reduction: partials[(ordinal * B + b) * nch + chunk]
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ part,
+                                                     const int32_t* __restrict__ csr, int n_weights,
+                                                     int n_inputs, int B, int64_t nch,
+                                                     double* __restrict__ gw,
+                                                     double* __restrict__ gx) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int o = blockIdx.x;  // output index: weights first, then (b, input)
+    double s = 0.0;
+    int j, b0, b1;
+    const int32_t* list;
+    int nl;
+    if (o < n_weights) {
+        j = o;
+        list = csr + csr[j];
+        nl = csr[j + 1] - csr[j];
+        b0 = 0;
+        b1 = B;
+    } else {
+        const int r = o - n_weights;
+        const int b = r / n_inputs;
+        j = r % n_inputs;
+        const int32_t* xo = csr + n_weights + 1;
+        list = csr + xo[j];
+        nl = xo[j + 1] - xo[j];
+        b0 = b;
+        b1 = b + 1;
+    }
+    const int64_t per = (int64_t)(b1 - b0) * nch;
+    for (int l = 0; l < nl; ++l) {
+        const double* base = part + ((size_t)list[l] * B + b0) * nch;
+        for (int64_t e = t; e < per; e += 256) s += base[e];
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (o < n_weights) gw[j] = red[0];
+        else if (gx) gx[(size_t)b0 * n_inputs + j] = red[0];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// plain method (one sweep per gate)
+// ----------------------------------------------------------------------------
+constexpr int kPgItems = 4;
+
+__device__ __forceinline__ void pair_apply(int cls, const M2& M, float2& x, float2& y) {
+    float2 u, v;
+    switch (cls) {
+    case OP_SWAP: u = y; v = x; break;
+    case OP_REAL:
+        u = make_float2(M.m00.x * x.x + M.m01.x * y.x, M.m00.x * x.y + M.m01.x * y.y);
+        v = make_float2(M.m10.x * x.x + M.m11.x * y.x, M.m10.x * x.y + M.m11.x * y.y);
+        break;
+    case OP_RXL: {
+        const float a = M.m00.x, bb = M.m01.y;
+        u = make_float2(a * x.x - bb * y.y, a * x.y + bb * y.x);
+        v = make_float2(a * y.x - bb * x.y, a * y.y + bb * x.x);
+        break;
+    }
+    default: {
+        const float2 p = cmul(M.m00, x), q = cmul(M.m01, y), r = cmul(M.m10, x), s = cmul(M.m11, y);
+        u = make_float2(p.x + q.x, p.y + q.y);
+        v = make_float2(r.x + s.x, r.y + s.y);
+        break;
+    }
+    }
+    x = u;
+    y = v;
+}
+
+__global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, int W, int64_t B,
+                                                  PGate pg, const float* __restrict__ mats,
+                                                  int n_shared, int n_ps) {
+    const int64_t base = ((int64_t)blockIdx.x * kPgItems) * 256 + threadIdx.x;
+    if (pg.cls == OP_DIAG) {
+        const int64_t total = B << W;
+        for (int i = 0; i < kPgItems; ++i) {
+            const int64_t it = base + i * 256;
+            if (it >= total) return;
+            const int b = (int)(it >> W);
+            const M2 M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
+            const float2 ph = ((it >> pg.tsh) & 1) ? M.m11 : M.m00;
+            state[it] = cmul(ph, state[it]);
+        }
+    } else if (pg.cls == OP_SIGN) {
+        const int64_t total = B << (W - 2);
+        const int lo = min(pg.tsh, pg.sh2), hi = max(pg.tsh, pg.sh2);
+        for (int i = 0; i < kPgItems; ++i) {
+            const int64_t it = base + i * 256;
+            if (it >= total) return;
+            const int64_t idx = insert_bit(insert_bit(it, lo, 1), hi, 1);
+            const float2 a = state[idx];
+            state[idx] = make_float2(-a.x, -a.y);
+        }
+    } else {
+        const int nctl = pg.csh >= 0 ? 1 : 0;
+        const int64_t total = B << (W - 1 - nctl);
+        for (int i = 0; i < kPgItems; ++i) {
+            const int64_t it = base + i * 256;
+            if (it >= total) return;
+            int64_t i0;
+            if (nctl) {
+                const int lo = min(pg.tsh, pg.csh), hi = max(pg.tsh, pg.csh);
+                i0 = insert_bit(insert_bit(it, lo, lo == pg.csh), hi, hi == pg.csh);
+            } else {
+                i0 = insert_bit(it, pg.tsh, 0);
+            }
+            const int64_t i1 = i0 | (int64_t(1) << pg.tsh);
+            const int b = (int)(i0 >> W);
+            M2 M{};
+            if (pg.cls != OP_SWAP) M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
+            float2 x = state[i0], y = state[i1];
+            pair_apply(pg.cls, M, x, y);
+            state[i0] = x;
+            state[i1] = y;
+        }
+    }
+}
+
+// lambda = D psi_N with D(idx) = sum_i g[b,i] (1 - 2 bit_i(idx)); psi copied to the workspace.
+__global__ __launch_bounds__(256) void k_adj_init(const float2* __restrict__ psiN,
+                                                  float2* __restrict__ psi, float2* __restrict__ lam,
+                                                  int W, int64_t B, const double* __restrict__ g) {
+    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (it >= (B << W)) return;
+    const int64_t b = it >> W;
+    const int64_t idx = it & ((int64_t(1) << W) - 1);
+    double d = 0.0;
+    for (int i = 0; i < W; ++i) {
+        const double gi = g[b * W + i];
+        d += ((idx >> (W - 1 - i)) & 1) ? -gi : gi;
+    }
+    const float2 a = psiN[it];
+    psi[it] = a;
+    lam[it] = make_float2((float)d * a.x, (float)d * a.y);
+}
+
+// Plain-method backward step for one gate: gradient partial at psi_k, lambda_k,
+// then psi <- U^dagger psi, lambda <- U^dagger lambda. Grid (nch, B).
+__global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2* __restrict__ lam,
+                                                int W, int B, PGate pg,
+                                                const float* __restrict__ mats, int n_shared,
+                                                int n_ps, double* __restrict__ part, int64_t nch) {
+    __shared__ double red[4];
+    const int t = threadIdx.x;
+    const int b = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    const size_t off = (size_t)b << W;
+    float2* P = psi + off;
+    float2* L = lam + off;
+    float acc = 0.f;
+    M2 M{};
+    if (pg.cls != OP_SWAP && pg.cls != OP_SIGN) M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
+    if (pg.cls == OP_DIAG) {
+        const int64_t n = int64_t(1) << W, per = n / nch;
+        for (int64_t e = t; e < per; e += 256) {
+            const int64_t idx = chunk * per + e;
+            const int bit = (idx >> pg.tsh) & 1;
+            float2 p = P[idx], l = L[idx];
+            if (pg.grad == OP_GZ) acc += bit ? -im_conj_mul(l, p) : im_conj_mul(l, p);
+            const float2 ph = bit ? M.m11 : M.m00;
+            P[idx] = cmul(ph, p);
+            L[idx] = cmul(ph, l);
+        }
+    } else if (pg.cls == OP_SIGN) {
+        const int64_t n = int64_t(1) << (W - 2), per = n / nch;
+        const int lo = min(pg.tsh, pg.sh2), hi = max(pg.tsh, pg.sh2);
+        for (int64_t e = t; e < per; e += 256) {
+            const int64_t idx = insert_bit(insert_bit(chunk * per + e, lo, 1), hi, 1);
+            const float2 p = P[idx], l = L[idx];
+            P[idx] = make_float2(-p.x, -p.y);
+            L[idx] = make_float2(-l.x, -l.y);
+        }
+    } else {
+        const int nctl = pg.csh >= 0 ? 1 : 0;
+        const int64_t n = int64_t(1) << (W - 1 - nctl), per = n / nch;
+        const int lo = nctl ? min(pg.tsh, pg.csh) : pg.tsh;
+        const int hi = nctl ? max(pg.tsh, pg.csh) : pg.tsh;
+        for (int64_t e = t; e < per; e += 256) {
+            const int64_t it = chunk * per + e;
+            const int64_t i0 = nctl ? insert_bit(insert_bit(it, lo, lo == pg.csh), hi, hi == pg.csh)
+                                    : insert_bit(it, pg.tsh, 0);
+            const int64_t i1 = i0 | (int64_t(1) << pg.tsh);
+            float2 p0 = P[i0], p1 = P[i1], l0 = L[i0], l1 = L[i1];
+            if (pg.grad == OP_GX) acc += im_conj_mul(l0, p1) + im_conj_mul(l1, p0);
+            else if (pg.grad == OP_GY) acc += re_conj_mul(l1, p0) - re_conj_mul(l0, p1);
+            pair_apply(pg.cls, M, p0, p1);
+            pair_apply(pg.cls, M, l0, l1);
+            P[i0] = p0; P[i1] = p1; L[i0] = l0; L[i1] = l1;
+        }
+    }
+    if (pg.slot >= 0) {
+        const double r = wave_sum((double)acc);
+        if ((t & 63) == 0) red[t >> 6] = r;
+        __syncthreads();
+        if (t == 0) part[((size_t)pg.slot * B + b) * nch + chunk] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// fused passes
+// ----------------------------------------------------------------------------
+// Register position p of a thread's 16 amplitudes <-> local tile bit reg[p].
+// Thread bits fill the other local bits in ascending order.
+struct Lay {
+    int lT, gT;          // thread part of the local / global index
+    int lr[kRegBits];    // 1 << reg[p]
+    int gr[kRegBits];    // 1 << lq[reg[p]]
+};
+
+__device__ __forceinline__ void make_layout(const DPass* __restrict__ P, int m, const int* reg,
+                                            int t, int tile_base, Lay& L) {
+    L.lT = 0;
+    L.gT = tile_base;
+    int i = 0;
+    for (int j = 0; j < m; ++j) {
+        if (j == reg[0] || j == reg[1] || j == reg[2] || j == reg[3]) continue;
+        const int bit = (t >> i) & 1;
+        ++i;
+        L.lT |= bit << j;
+        L.gT |= bit << P->lq[j];
+    }
+    for (int p = 0; p < kRegBits; ++p) {
+        L.lr[p] = 1 << reg[p];
+        L.gr[p] = 1 << P->lq[reg[p]];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ int reg_part(const int* parts) {
+    return ((K & 1) ? parts[0] : 0) | ((K & 2) ? parts[1] : 0) | ((K & 4) ? parts[2] : 0) |
+           ((K & 8) ? parts[3] : 0);
+}
+
+template <int K = 0>
+__device__ __forceinline__ void lds_store(float2* lds, const Lay& L, const float2 (&a)[kRegs]) {
+    if constexpr (K < kRegs) {
+        lds[swz(L.lT | reg_part<K>(L.lr))] = a[K];
+        lds_store<K + 1>(lds, L, a);
+    }
+}
+template <int K = 0>
+__device__ __forceinline__ void lds_load(const float2* lds, const Lay& L, float2 (&a)[kRegs]) {
+    if constexpr (K < kRegs) {
+        a[K] = lds[swz(L.lT | reg_part<K>(L.lr))];
+        lds_load<K + 1>(lds, L, a);
+    }
+}
+template <int K = 0>
+__device__ __forceinline__ void g_load(const float2* st, const Lay& L, float2 (&a)[kRegs]) {
+    if constexpr (K < kRegs) {
+        a[K] = st[L.gT | reg_part<K>(L.gr)];
+        g_load<K + 1>(st, L, a);
+    }
+}
+template <int K = 0>
+__device__ __forceinline__ void g_store(float2* st, const Lay& L, const float2 (&a)[kRegs]) {
+    if constexpr (K < kRegs) {
+        st[L.gT | reg_part<K>(L.gr)] = a[K];
+        g_store<K + 1>(st, L, a);
+    }
+}
+
+// --- register ops, templated on the target's register position P ---
+template <int P, bool CTL>
+__device__ __forceinline__ void r_u2(float2 (&a)[kRegs], const M2& M, int cm) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        if (k & (1 << P)) continue;
+        const int k1 = k | (1 << P);
+        const float2 x = a[k], y = a[k1];
+        const float2 p = cmul(M.m00, x), q = cmul(M.m01, y), r = cmul(M.m10, x), s = cmul(M.m11, y);
+        const float2 u = make_float2(p.x + q.x, p.y + q.y), v = make_float2(r.x + s.x, r.y + s.y);
+        if (CTL) {
+            const bool c = (cm >> k) & 1;
+            a[k] = c ? u : x;
+            a[k1] = c ? v : y;
+        } else {
+            a[k] = u;
+            a[k1] = v;
+        }
+    }
+}
+
+template <int P, bool CTL>
+__device__ __forceinline__ void r_real(float2 (&a)[kRegs], const M2& M, int cm) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        if (k & (1 << P)) continue;
+        const int k1 = k | (1 << P);
+        const float2 x = a[k], y = a[k1];
+        const float2 u = make_float2(M.m00.x * x.x + M.m01.x * y.x, M.m00.x * x.y + M.m01.x * y.y);
+        const float2 v = make_float2(M.m10.x * x.x + M.m11.x * y.x, M.m10.x * x.y + M.m11.x * y.y);
+        if (CTL) {
+            const bool c = (cm >> k) & 1;
+            a[k] = c ? u : x;
+            a[k1] = c ? v : y;
+        } else {
+            a[k] = u;
+            a[k1] = v;
+        }
+    }
+}
+
+template <int P, bool CTL>
+__device__ __forceinline__ void r_rxl(float2 (&a)[kRegs], const M2& M, int cm) {
+    const float al = M.m00.x, be = M.m01.y;
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        if (k & (1 << P)) continue;
+        const int k1 = k | (1 << P);
+        const float2 x = a[k], y = a[k1];
+        const float2 u = make_float2(al * x.x - be * y.y, al * x.y + be * y.x);
+        const float2 v = make_float2(al * y.x - be * x.y, al * y.y + be * x.x);
+        if (CTL) {
+            const bool c = (cm >> k) & 1;
+            a[k] = c ? u : x;
+            a[k1] = c ? v : y;
+        } else {
+            a[k] = u;
+            a[k1] = v;
+        }
+    }
+}
+
+template <int P, bool CTL>
+__device__ __forceinline__ void r_swap(float2 (&a)[kRegs], int cm) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        if (k & (1 << P)) continue;
+        const int k1 = k | (1 << P);
+        const float2 x = a[k], y = a[k1];
+        if (CTL) {
+            const bool c = (cm >> k) & 1;
+            a[k] = c ? y : x;
+            a[k1] = c ? x : y;
+        } else {
+            a[k] = y;
+            a[k1] = x;
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void r_diag(float2 (&a)[kRegs], const M2& M) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) a[k] = cmul((k & (1 << P)) ? M.m11 : M.m00, a[k]);
+}
+
+__device__ __forceinline__ void r_phase_all(float2 (&a)[kRegs], float2 ph) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) a[k] = cmul(ph, a[k]);
+}
+
+__device__ __forceinline__ void r_flip(float2 (&a)[kRegs], int flip) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        const unsigned s = (unsigned)((flip >> k) & 1) << 31;
+        a[k] = make_float2(__uint_as_float(__float_as_uint(a[k].x) ^ s),
+                           __uint_as_float(__float_as_uint(a[k].y) ^ s));
+    }
+}
+
+template <int P, bool CTL>
+__device__ __forceinline__ float r_gx(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs], int cm) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        if (k & (1 << P)) continue;
+        const int k1 = k | (1 << P);
+        const float v = im_conj_mul(lm[k], ps[k1]) + im_conj_mul(lm[k1], ps[k]);
+        acc += (!CTL || ((cm >> k) & 1)) ? v : 0.f;
+    }
+    return acc;
+}
+template <int P>
+__device__ __forceinline__ float r_gy(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs]) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        if (k & (1 << P)) continue;
+        const int k1 = k | (1 << P);
+        acc += re_conj_mul(lm[k1], ps[k]) - re_conj_mul(lm[k], ps[k1]);
+    }
+    return acc;
+}
+template <int P>
+__device__ __forceinline__ float r_gz(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs]) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) {
+        const float v = im_conj_mul(lm[k], ps[k]);
+        acc += (k & (1 << P)) ? -v : v;
+    }
+    return acc;
+}
+__device__ __forceinline__ float r_gz_all(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs]) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) acc += im_conj_mul(lm[k], ps[k]);
+    return acc;
+}
+
+// 16-bit mask of the registers whose control qubit is 1.
+__device__ __forceinline__ int ctl_mask(int ctl, int gT) {
+    if (ctl < 0) return 0xFFFF;
+    switch (ctl) {
+    case 0: return 0xAAAA;
+    case 1: return 0xCCCC;
+    case 2: return 0xF0F0;
+    case 3: return 0xFF00;
+    default: return ((gT >> (ctl & 0xFF)) & 1) ? 0xFFFF : 0;
+    }
+}
+
+#define QSV_DISPATCH_POS(pos, CALL) \
+    switch (pos) {                  \
+    case 0: CALL(0); break;         \
+    case 1: CALL(1); break;         \
+    case 2: CALL(2); break;         \
+    default: CALL(3); break;        \
+    }
+
+// Apply one non-gradient op to one register set.
+__device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], const M2& M, int gT,
+                                         const DTerm* __restrict__ terms) {
+    const bool ctl = op.ctl >= 0;
+    const int cm = ctl_mask(op.ctl, gT);
+    switch (op.kind) {
+    case OP_U2:
+#define C_(P) if (ctl) r_u2<P, true>(a, M, cm); else r_u2<P, false>(a, M, cm)
+        QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+        break;
+    case OP_REAL:
+#define C_(P) if (ctl) r_real<P, true>(a, M, cm); else r_real<P, false>(a, M, cm)
+        QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+        break;
+    case OP_RXL:
+#define C_(P) if (ctl) r_rxl<P, true>(a, M, cm); else r_rxl<P, false>(a, M, cm)
+        QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+        break;
+    case OP_SWAP:
+#define C_(P) if (ctl) r_swap<P, true>(a, cm); else r_swap<P, false>(a, cm)
+        QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+        break;
+    case OP_DIAG:
+        if (op.pos >= 0) {
+#define C_(P) r_diag<P>(a, M)
+            QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+        } else {
+            r_phase_all(a, ((gT >> op.sh) & 1) ? M.m11 : M.m00);
+        }
+        break;
+    case OP_SIGN: {
+        int flip = op.pos;
+        for (int i = 0; i < op.nterm; ++i) {
+            const DTerm tm = terms[op.term0 + i];
+            if (tm.s1 < 0) {
+                if ((gT >> tm.s0) & 1) flip ^= tm.mask;
+            } else if ((gT >> tm.s0) & (gT >> tm.s1) & 1) {
+                flip ^= 0xFFFF;
+            }
+        }
+        r_flip(a, flip);
+        break;
+    }
+    default: break;
+    }
+}
+
+__device__ __forceinline__ float grad_op(const DOp& op, const float2 (&ps)[kRegs],
+                                         const float2 (&lm)[kRegs], int gT) {
+    float v = 0.f;
+    if (op.kind == OP_GX) {
+        const bool ctl = op.ctl >= 0;
+        const int cm = ctl_mask(op.ctl, gT);
+#define C_(P) v = ctl ? r_gx<P, true>(ps, lm, cm) : r_gx<P, false>(ps, lm, cm)
+        QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+    } else if (op.kind == OP_GY) {
+#define C_(P) v = r_gy<P>(ps, lm)
+        QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+    } else {
+        if (op.pos >= 0) {
+#define C_(P) v = r_gz<P>(ps, lm)
+            QSV_DISPATCH_POS(op.pos, C_)
+#undef C_
+        } else {
+            v = r_gz_all(ps, lm);
+            if ((gT >> op.sh) & 1) v = -v;
+        }
+    }
+    return v;
+}
+
+__device__ __forceinline__ bool same_reg(const int* a, const int* b) {
+    return a[0] == b[0] && a[1] == b[1] && a[2] == b[2] && a[3] == b[3];
+}
+
+__device__ __forceinline__ int tile_base_of(const DPass* __restrict__ P, int tbits, int64_t tis) {
+    int base = 0;
+    for (int k = 0; k < tbits; ++k) base |= (int)((tis >> k) & 1) << P->oq[k];
+    return base;
+}
+
+__global__ __launch_bounds__(1024) void k_pass_fwd(const DPass* __restrict__ P,
+                                                   const DStage* __restrict__ S,
+                                                   const DOp* __restrict__ O,
+                                                   const DTerm* __restrict__ Tm,
+                                                   const float* __restrict__ mats, int n_shared,
+                                                   int n_ps, float2* __restrict__ state, int W) {
+    extern __shared__ float2 lds[];
+    const int m = P->m;
+    const int t = threadIdx.x;
+    const bool act = t < (1 << (m - kRegBits));
+    const int tbits = W - m;
+    const int64_t tile = blockIdx.x;
+    const int b = (int)(tile >> tbits);
+    const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
+    const int base = tile_base_of(P, tbits, tis);
+    float2* st = state + ((size_t)b << W);
+
+    int cur[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
+    Lay L;
+    make_layout(P, m, cur, t, base, L);
+    float2 a[kRegs];
+    if (act) g_load(st, L, a);
+    else for (int k = 0; k < kRegs; ++k) a[k] = make_float2(0.f, 0.f);
+
+    for (int s = 0; s < P->n_stages; ++s) {
+        const DStage& stg = S[P->stage0 + s];
+        if (!same_reg(cur, stg.reg)) {
+            if (act) lds_store(lds, L, a);
+            __syncthreads();
+            for (int p = 0; p < kRegBits; ++p) cur[p] = stg.reg[p];
+            make_layout(P, m, cur, t, base, L);
+            if (act) lds_load(lds, L, a);
+            __syncthreads();
+        }
+        for (int oi = stg.op0; oi < stg.op1; ++oi) {
+            const DOp op = O[oi];
+            M2 M{};
+            if (op.kind != OP_SIGN && op.kind != OP_SWAP) M = load_m2(mat_ptr(mats, op.mat, b, n_shared, n_ps));
+            apply_op(op, a, M, L.gT, Tm);
+        }
+    }
+    const int nat[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
+    if (!same_reg(cur, nat)) {
+        if (act) lds_store(lds, L, a);
+        __syncthreads();
+        make_layout(P, m, nat, t, base, L);
+        if (act) lds_load(lds, L, a);
+    }
+    if (act) g_store(st, L, a);
+}
+
+__global__ __launch_bounds__(256) void k_pass_bwd(
+    const DPass* __restrict__ P, const DStage* __restrict__ S, const DOp* __restrict__ O,
+    const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
+    const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
+    float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int W,
+    int B, double* __restrict__ part) {
+    extern __shared__ float2 lds[];
+    const int m = P->m;
+    const int t = threadIdx.x;
+    const int nthr = 1 << (m - kRegBits);
+    const bool act = t < nthr;
+    const int nwaves = (int)(blockDim.x >> 6);
+    double* red = reinterpret_cast<double*>(lds + (1 << m));
+    const int tbits = W - m;
+    const int64_t tile = blockIdx.x;
+    const int b = (int)(tile >> tbits);
+    const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
+    const int base = tile_base_of(P, tbits, tis);
+    const size_t off = (size_t)b << W;
+    const int flags = P->flags;
+
+    int cur[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
+    Lay L;
+    make_layout(P, m, cur, t, base, L);
+    float2 ps[kRegs], lm[kRegs];
+    for (int k = 0; k < kRegs; ++k) ps[k] = lm[k] = make_float2(0.f, 0.f);
+    if (act) {
+        if (flags & PF_FIRST_BWD) {
+            g_load(psiN + off, L, ps);
+            // lambda = D psi, D(idx) = G0 - 2 sum_{i: bit_i = 1} g_i (additive over bits)
+            const double* g = gout + (size_t)b * W;
+            double G0 = 0.0, DT = 0.0;
+            for (int i = 0; i < W; ++i) {
+                G0 += g[i];
+                if ((L.gT >> (W - 1 - i)) & 1) DT += g[i];
+            }
+            double gp[kRegBits];
+            for (int p = 0; p < kRegBits; ++p) gp[p] = g[W - 1 - P->lq[cur[p]]];
+#pragma unroll
+            for (int k = 0; k < kRegs; ++k) {
+                double dr = DT;
+                for (int p = 0; p < kRegBits; ++p)
+                    if ((k >> p) & 1) dr += gp[p];
+                const float d = (float)(G0 - 2.0 * dr);
+                lm[k] = make_float2(d * ps[k].x, d * ps[k].y);
+            }
+        } else {
+            g_load(psi + off, L, ps);
+            g_load(lam + off, L, lm);
+        }
+    }
+    const int wave = t >> 6, lane = t & 63;
+    for (int s = 0; s < P->n_stages; ++s) {
+        const DStage& stg = S[P->stage0 + s];
+        if (!same_reg(cur, stg.reg)) {
+            Lay Ln;
+            for (int p = 0; p < kRegBits; ++p) cur[p] = stg.reg[p];
+            make_layout(P, m, cur, t, base, Ln);
+            if (act) lds_store(lds, L, ps);
+            __syncthreads();
+            if (act) lds_load(lds, Ln, ps);
+            __syncthreads();
+            if (act) lds_store(lds, L, lm);
+            __syncthreads();
+            if (act) lds_load(lds, Ln, lm);
+            __syncthreads();
+            L = Ln;
+        }
+        for (int oi = stg.op0; oi < stg.op1; ++oi) {
+            const DOp op = O[oi];
+            if (op.kind >= OP_GX) {
+                const double r = wave_sum((double)grad_op(op, ps, lm, L.gT));
+                if (lane == 0) red[wave * P->n_gslots + op.slot] = r;
+            } else {
+                M2 M{};
+                if (op.kind != OP_SIGN && op.kind != OP_SWAP) M = load_m2(mat_ptr(mats, op.mat, b, n_shared, n_ps));
+                apply_op(op, ps, M, L.gT, Tm);
+                apply_op(op, lm, M, L.gT, Tm);
+            }
+        }
+    }
+    if (!(flags & PF_LAST_BWD)) {
+        const int nat[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
+        if (!same_reg(cur, nat)) {
+            Lay Ln;
+            make_layout(P, m, nat, t, base, Ln);
+            if (act) lds_store(lds, L, ps);
+            __syncthreads();
+            if (act) lds_load(lds, Ln, ps);
+            __syncthreads();
+            if (act) lds_store(lds, L, lm);
+            __syncthreads();
+            if (act) lds_load(lds, Ln, lm);
+            L = Ln;
+        }
+        if (act) {
+            g_store(psi + off, L, ps);
+            g_store(lam + off, L, lm);
+        }
+    }
+    __syncthreads();
+    const int ng = P->n_gslots;
+    const int64_t nch = int64_t(1) << tbits;
+    for (int j = t; j < ng; j += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += red[w * ng + j];
+        part[((size_t)gslot_map[P->gslot0 + j] * B + b) * nch + tis] = s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// host side: device tables
+// ----------------------------------------------------------------------------
+namespace {
+
+template <class T>
+size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int get_tables(const qsv_plan_t* p, DeviceTables** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(p->dev_mu);
+    auto it = p->dev.find(dev);
+    if (it != p->dev.end()) {
+        *out = &it->second;
+        return QSV_OK;
+    }
+    DeviceTables t;
+    const size_t sizes[] = {bytes_of(p->dgates), bytes_of(p->recipes), bytes_of(p->recipe_gates),
+                            bytes_of(p->fwd_pass), bytes_of(p->bwd_pass), bytes_of(p->stages),
+                            bytes_of(p->ops), bytes_of(p->terms), bytes_of(p->gslot_map),
+                            bytes_of(p->prefix_mat), bytes_of(p->grad_csr)};
+    const void* srcs[] = {p->dgates.data(), p->recipes.data(), p->recipe_gates.data(),
+                          p->fwd_pass.data(), p->bwd_pass.data(), p->stages.data(),
+                          p->ops.data(), p->terms.data(), p->gslot_map.data(),
+                          p->prefix_mat.data(), p->grad_csr.data()};
+    const int n = (int)(sizeof(sizes) / sizeof(sizes[0]));
+    size_t total = 0, offs[16];
+    for (int i = 0; i < n; ++i) { offs[i] = total; total += align256(std::max<size_t>(sizes[i], 1)); }
+    char* host = (char*)std::calloc(total, 1);
+    if (!host) { set_error("host allocation of plan tables failed"); return QSV_ERR_OOM; }
+    for (int i = 0; i < n; ++i)
+        if (sizes[i]) std::memcpy(host + offs[i], srcs[i], sizes[i]);
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, total);
+    if (e != hipSuccess) {
+        std::free(host);
+        set_error(std::string("hipMalloc of plan tables: ") + hipGetErrorString(e));
+        return QSV_ERR_OOM;
+    }
+    e = hipMemcpy(d, host, total, hipMemcpyHostToDevice);
+    std::free(host);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        set_error(std::string("hipMemcpy of plan tables: ") + hipGetErrorString(e));
+        return QSV_ERR_HIP;
+    }
+    char* c = (char*)d;
+    t.base = d;
+    t.gates = (DGate*)(c + offs[0]);
+    t.recipes = (DRecipe*)(c + offs[1]);
+    t.recipe_gates = (int32_t*)(c + offs[2]);
+    t.fwd_pass = (DPass*)(c + offs[3]);
+    t.bwd_pass = (DPass*)(c + offs[4]);
+    t.stages = (DStage*)(c + offs[5]);
+    t.ops = (DOp*)(c + offs[6]);
+    t.terms = (DTerm*)(c + offs[7]);
+    t.gslot_map = (int32_t*)(c + offs[8]);
+    t.prefix_mat = (int32_t*)(c + offs[9]);
+    t.grad_csr = (int32_t*)(c + offs[10]);
+    auto res = p->dev.emplace(dev, t);
+    *out = &res.first->second;
+    return QSV_OK;
+}
+
+size_t mats_bytes(const qsv_plan_t* p, int64_t B) {
+    return align256(((size_t)p->n_shared_mats + (size_t)B * p->n_ps_mats) * 8 * sizeof(float) + 32);
+}
+
+int64_t fused_nch(const qsv_plan_t* p) {
+    return int64_t(1) << (p->W - std::min(p->opts.tile_qubits, p->W));
+}
+
+int64_t pg_nch(const qsv_plan_t* p) {
+    const int64_t q = int64_t(1) << std::max(p->W - 2, 0);
+    return std::max<int64_t>(1, q / 1024);
+}
+
+int64_t grad_nch(const qsv_plan_t* p) {
+    return p->opts.method == QSV_METHOD_PER_GATE ? pg_nch(p) : fused_nch(p);
+}
+
+int64_t expval_nchunk(const qsv_plan_t* p) { return int64_t(1) << (p->W - std::min(p->W, 12)); }
+
+size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * ((size_t)1 << p->W) * 8; }
+
+int check_plan(const qsv_plan_t* p) {
+    if (!p || p->magic != kPlanMagic) {
+        set_error("null or destroyed plan");
+        return QSV_ERR_HANDLE;
+    }
+    return QSV_OK;
+}
+
+int run_coef(const qsv_plan_t* p, DeviceTables* T, const float* w, const float* x, int64_t B,
+             float* mats, hipStream_t s) {
+    const int nr = (int)p->recipes.size();
+    if (nr == 0) return QSV_OK;
+    dim3 grid((nr + 127) / 128, (unsigned)(p->n_ps_mats ? B : 1));
+    hipLaunchKernelGGL(k_coef, grid, dim3(128), 0, s, T->gates, T->recipes, T->recipe_gates, nr,
+                       w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, mats);
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+int run_init(const qsv_plan_t* p, DeviceTables* T, const float* mats, int64_t B, float2* st,
+             hipStream_t s) {
+    const int cb = std::min(p->W, 12);
+    dim3 grid((unsigned)(int64_t(1) << (p->W - cb)), (unsigned)B);
+    hipLaunchKernelGGL(k_init, grid, dim3(256), 0, s, st, p->W, T->prefix_mat, mats,
+                       p->n_shared_mats, p->n_ps_mats);
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+int check_batch(const qsv_plan_t* p, int64_t B) {
+    if (B <= 0) { set_error("batch must be positive"); return QSV_ERR_ARG; }
+    if (B > 65535) { set_error("batch above 65535 is not supported"); return QSV_ERR_ARG; }
+    if ((uint64_t)B > (uint64_t(1) << 40) >> p->W) { set_error("state too large"); return QSV_ERR_TOO_BIG; }
+    return QSV_OK;
+}
+
+size_t pass_lds_fwd(const qsv_plan_t* p) {
+    const int m = std::min(p->opts.tile_qubits, p->W);
+    return (size_t(1) << m) * 8;
+}
+
+size_t pass_lds_bwd(const qsv_plan_t* p) {
+    const int m = std::min(p->opts.tile_qubits, p->W);
+    const int threads = std::max(64, 1 << (m - kRegBits));
+    int maxg = 0;
+    for (auto& ps : p->bwd_pass) maxg = std::max(maxg, (int)ps.n_gslots);
+    return (size_t(1) << m) * 8 + (size_t)(threads / 64) * maxg * 8;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+const char* qsv_strerror(int code) {
+    switch (code) {
+    case QSV_OK: return "ok";
+    case QSV_ERR_ARG: return "invalid argument";
+    case QSV_ERR_QUBIT: return "qubit index out of range or repeated";
+    case QSV_ERR_GATE: return "unknown gate kind";
+    case QSV_ERR_PARAM: return "invalid angle source or index";
+    case QSV_ERR_TOO_BIG: return "circuit or state too large";
+    case QSV_ERR_OOM: return "out of memory";
+    case QSV_ERR_HIP: return "HIP runtime error";
+    case QSV_ERR_HANDLE: return "invalid plan handle";
+    default: return "unknown error";
+    }
+}
+
+const char* qsv_last_error(void) { return g_last_error.c_str(); }
+
+void qsv_default_opts(qsv_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->method = QSV_METHOD_FUSED;
+    o->fuse_width = 5;
+    o->tile_qubits = 12;
+    o->low_qubits = 5;
+    o->max_pass_grads = 256;
+}
+
+int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n_weights,
+             int32_t n_inputs, const qsv_opts* opts, qsv_plan_t** out) {
+    if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
+    *out = nullptr;
+    if (n_qubits < 1) { set_error("n_qubits must be >= 1"); return QSV_ERR_ARG; }
+    if (n_qubits > QSV_MAX_QUBITS) { set_error("n_qubits above QSV_MAX_QUBITS"); return QSV_ERR_TOO_BIG; }
+    if (n_gates < 0 || n_weights < 0 || n_inputs < 0) { set_error("negative count"); return QSV_ERR_ARG; }
+    if (n_gates > 0 && !gates) { set_error("gates is NULL"); return QSV_ERR_ARG; }
+    qsv_opts o;
+    qsv_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.method != QSV_METHOD_FUSED && o.method != QSV_METHOD_PER_GATE) { set_error("bad method"); return QSV_ERR_ARG; }
+    if (o.fuse_width < 1 || o.fuse_width > 16) { set_error("fuse_width must be in 1..16"); return QSV_ERR_ARG; }
+    if (o.tile_qubits < kRegBits || o.tile_qubits > kMaxTileQubits) { set_error("tile_qubits must be in 4..12"); return QSV_ERR_ARG; }
+    if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
+    if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
+    for (int g = 0; g < n_gates; ++g) {
+        const qsv_gate& G = gates[g];
+        char buf[160];
+        if (G.kind < QSV_H || G.kind > QSV_CRX) {
+            std::snprintf(buf, sizeof buf, "gate %d: unknown kind %d", g, G.kind);
+            set_error(buf);
+            return QSV_ERR_GATE;
+        }
+        const bool two = G.kind == QSV_CNOT || G.kind == QSV_CZ || G.kind == QSV_CRX;
+        if (G.q0 < 0 || G.q0 >= n_qubits || (two && (G.q1 < 0 || G.q1 >= n_qubits || G.q1 == G.q0))) {
+            std::snprintf(buf, sizeof buf, "gate %d: qubits (%d, %d) invalid for W = %d", g, G.q0, G.q1, n_qubits);
+            set_error(buf);
+            return QSV_ERR_QUBIT;
+        }
+        const bool param = G.kind == QSV_RX || G.kind == QSV_RY || G.kind == QSV_RZ || G.kind == QSV_CRX;
+        const bool ok_src = param ? (G.src == QSV_SRC_WEIGHT || G.src == QSV_SRC_INPUT) : G.src == QSV_SRC_NONE;
+        const bool ok_idx = G.src == QSV_SRC_WEIGHT ? (G.idx >= 0 && G.idx < n_weights)
+                          : G.src == QSV_SRC_INPUT ? (G.idx >= 0 && G.idx < n_inputs) : true;
+        if (!ok_src || !ok_idx) {
+            std::snprintf(buf, sizeof buf, "gate %d: angle source %d / index %d invalid", g, G.src, G.idx);
+            set_error(buf);
+            return QSV_ERR_PARAM;
+        }
+    }
+    qsv_plan_t* p = new (std::nothrow) qsv_plan_t();
+    if (!p) { set_error("plan allocation failed"); return QSV_ERR_OOM; }
+    p->magic = kPlanMagic;
+    p->W = n_qubits;
+    p->n_gates = n_gates;
+    p->n_weights = n_weights;
+    p->n_inputs = n_inputs;
+    if (o.method == QSV_METHOD_FUSED && n_qubits < kRegBits) o.method = QSV_METHOD_PER_GATE;
+    p->opts = o;
+    p->gates.assign(gates, gates + n_gates);
+    int rc;
+    try {
+        rc = build_plan(p);
+    } catch (const std::bad_alloc&) {
+        rc = QSV_ERR_OOM;
+        set_error("out of host memory while planning");
+    }
+    if (rc != QSV_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return QSV_OK;
+}
+
+void qsv_plan_destroy(qsv_plan_t* p) {
+    if (!p || p->magic != kPlanMagic) return;
+    p->magic = 0;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    for (auto& kv : p->dev) {
+        if (hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second.base);
+    }
+    if (have && !p->dev.empty()) (void)hipSetDevice(cur);
+    delete p;
+}
+
+int qsv_plan_get_info(const qsv_plan_t* p, qsv_plan_info* info) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!info) { set_error("info is NULL"); return QSV_ERR_ARG; }
+    std::memset(info, 0, sizeof *info);
+    info->n_qubits = p->W;
+    info->n_gates = p->n_gates;
+    info->n_weights = p->n_weights;
+    info->n_inputs = p->n_inputs;
+    info->method = p->opts.method;
+    info->fuse_width = p->opts.fuse_width;
+    info->tile_qubits = std::min(p->opts.tile_qubits, p->W);
+    info->low_qubits = p->opts.low_qubits;
+    info->n_prefix_gates = (int32_t)p->prefix_gates.size();
+    info->n_blocks = (int32_t)p->blocks.size();
+    if (p->opts.method == QSV_METHOD_PER_GATE) {
+        info->n_fwd_passes = (int32_t)p->pg_fwd.size();
+        info->n_bwd_passes = (int32_t)p->pg_bwd.size();
+    } else {
+        info->n_fwd_passes = (int32_t)p->fwd_pass.size();
+        info->n_bwd_passes = (int32_t)p->bwd_pass.size();
+    }
+    info->n_fwd_stages = p->n_fwd_stages;
+    info->n_bwd_stages = p->n_bwd_stages;
+    info->n_param_gates = p->n_param;
+    info->n_recipes = (int32_t)p->recipes.size();
+    return QSV_OK;
+}
+
+int qsv_plan_gate_order(const qsv_plan_t* p, int32_t which, int32_t* order) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!order || (which != 0 && which != 1)) { set_error("bad arguments"); return QSV_ERR_ARG; }
+    const auto& v = which == 0 ? p->fwd_order : p->bwd_order;
+    std::copy(v.begin(), v.end(), order);
+    return QSV_OK;
+}
+
+int qsv_plan_gate_blocks(const qsv_plan_t* p, int32_t* block_of_gate) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!block_of_gate) { set_error("block_of_gate is NULL"); return QSV_ERR_ARG; }
+    std::copy(p->block_of_gate.begin(), p->block_of_gate.end(), block_of_gate);
+    return QSV_OK;
+}
+
+size_t qsv_workspace_size(const qsv_plan_t* p, int64_t B, int32_t op) {
+    if (check_plan(p) || B <= 0) return 0;
+    switch (op) {
+    case QSV_OP_FORWARD: return mats_bytes(p, B);
+    case QSV_OP_EXPVAL: return align256((size_t)B * expval_nchunk(p) * p->W * sizeof(double));
+    case QSV_OP_BACKWARD:
+        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) +
+               align256((size_t)std::max(p->n_param, 1) * B * grad_nch(p) * sizeof(double));
+    default: return 0;
+    }
+}
+
+int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
+                void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!d_state || (p->n_weights && !w) || (p->n_inputs && !x)) { set_error("null pointer"); return QSV_ERR_ARG; }
+    const size_t need = qsv_workspace_size(p, B, QSV_OP_FORWARD);
+    if (!ws || ws_bytes < need) { set_error("forward workspace too small"); return QSV_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    DeviceTables* T;
+    if ((rc = get_tables(p, &T))) return rc;
+    float* mats = (float*)ws;
+    float2* st = (float2*)d_state;
+    if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
+    if ((rc = run_init(p, T, mats, B, st, s))) return rc;
+    const int W = p->W;
+    if (p->opts.method == QSV_METHOD_PER_GATE) {
+        for (const PGate& pg : p->pg_fwd) {
+            int64_t items;
+            if (pg.cls == OP_DIAG) items = B << W;
+            else if (pg.cls == OP_SIGN) items = B << (W - 2);
+            else items = B << (W - 1 - (pg.csh >= 0 ? 1 : 0));
+            const int64_t blocks = (items + 256 * kPgItems - 1) / (256 * kPgItems);
+            hipLaunchKernelGGL(k_pg_apply, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
+                               (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+        }
+        HIP_TRY(hipGetLastError());
+        return QSV_OK;
+    }
+    const int m = std::min(p->opts.tile_qubits, W);
+    const unsigned threads = (unsigned)std::max(64, 1 << (m - kRegBits));
+    const unsigned tiles = (unsigned)(B << (W - m));
+    const size_t lds = pass_lds_fwd(p);
+    for (size_t i = 0; i < p->fwd_pass.size(); ++i) {
+        hipLaunchKernelGGL(k_pass_fwd, dim3(tiles), dim3(threads), lds, s, T->fwd_pass + i,
+                           T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
+                           p->n_ps_mats, st, W);
+    }
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out, void* ws,
+               size_t ws_bytes, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!d_state || !out) { set_error("null pointer"); return QSV_ERR_ARG; }
+    const size_t need = qsv_workspace_size(p, B, QSV_OP_EXPVAL);
+    if (!ws || ws_bytes < need) { set_error("expval workspace too small"); return QSV_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nchunk = expval_nchunk(p);
+    double* part = (double*)ws;
+    hipLaunchKernelGGL(k_expval_part, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
+                       (const float2*)d_state, p->W, part);
+    hipLaunchKernelGGL(k_expval_final, dim3((unsigned)p->W, (unsigned)B), dim3(256), 0, s,
+                       (const double*)part, p->W, nchunk, out);
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
+                 const void* d_state, const double* gout, void* ws, size_t ws_bytes, double* gw,
+                 double* gx, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!d_state || !gout || (p->n_weights && !w) || (p->n_inputs && !x) || (p->n_weights && !gw)) {
+        set_error("null pointer");
+        return QSV_ERR_ARG;
+    }
+    const size_t need = qsv_workspace_size(p, B, QSV_OP_BACKWARD);
+    if (!ws || ws_bytes < need) { set_error("backward workspace too small"); return QSV_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    DeviceTables* T;
+    if ((rc = get_tables(p, &T))) return rc;
+    const int W = p->W;
+    char* c = (char*)ws;
+    float* mats = (float*)c;
+    c += mats_bytes(p, B);
+    float2* psi = (float2*)c;
+    c += align256(state_bytes(p, B));
+    float2* lam = (float2*)c;
+    c += align256(state_bytes(p, B));
+    double* part = (double*)c;
+    if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
+    const int64_t nch = grad_nch(p);
+    if (p->opts.method == QSV_METHOD_PER_GATE) {
+        const int64_t n = B << W;
+        hipLaunchKernelGGL(k_adj_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const float2*)d_state, psi, lam, W, B, gout);
+        for (const PGate& pg : p->pg_bwd) {
+            hipLaunchKernelGGL(k_pg_adj, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi,
+                               lam, W, (int)B, pg, (const float*)mats, p->n_shared_mats,
+                               p->n_ps_mats, part, nch);
+        }
+    } else {
+        const int m = std::min(p->opts.tile_qubits, W);
+        const unsigned threads = (unsigned)std::max(64, 1 << (m - kRegBits));
+        const unsigned tiles = (unsigned)(B << (W - m));
+        const size_t lds = pass_lds_bwd(p);
+        for (size_t i = 0; i < p->bwd_pass.size(); ++i) {
+            hipLaunchKernelGGL(k_pass_bwd, dim3(tiles), dim3(threads), lds, s, T->bwd_pass + i,
+                               T->stages, T->ops, T->terms, T->gslot_map, (const float*)mats,
+                               p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
+                               gout, W, (int)B, part);
+        }
+    }
+    const int n_out = p->n_weights + (gx ? (int)B * p->n_inputs : 0);
+    if (n_out > 0)
+        hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)n_out), dim3(256), 0, s,
+                           (const double*)part, T->grad_csr, p->n_weights, p->n_inputs, (int)B, nch,
+                           gw, gx);
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+"""Shared test helpers: tolerance checks and runners for the GPU path and the oracle."""
+import numpy as np
+
+AMP_TOL = 1e-5      # max-abs on amplitudes
+EXP_TOL = 1e-5      # max-abs on <Z_i>
+GRAD_TOL = 1e-4     # relative on gradients (normwise and per entry with a floor)
+
+
+def grad_close(got, ref, tol=GRAD_TOL):
+    """Normwise ||g - g*||_inf <= tol ||g*||_inf, and per entry
+    |g - g*| <= tol * max(|g*|, 1e-2 ||g*||_inf)."""
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    if ref.size == 0:
+        return True, 0.0
+    scale = max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref)
+    norm_ok = err.max() <= tol * scale
+    entry_ok = bool(np.all(err <= tol * np.maximum(np.abs(ref), 1e-2 * scale)))
+    return bool(norm_ok and entry_ok), float(err.max() / scale)
+
+
+def gpu_run(circ, w, x, batch, g=None, method="fused", **opts):
+    """Forward + readout (+ backward if g is given) through the C ABI on cuda:0."""
+    import torch
+
+    from paper_2404_09213_amd import binding
+    dev = torch.device("cuda:0")
+    plan = binding.Plan(circ.n_qubits, circ.gates, circ.n_weights, circ.n_inputs, method=method,
+                        **opts)
+    wt = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    st = plan.forward(wt, xt, batch)
+    E = plan.expval(st)
+    out = {"state": st, "E": E, "plan": plan}
+    if g is not None:
+        gw, gx = plan.backward(wt, xt, st, torch.from_numpy(np.ascontiguousarray(g)).to(dev))
+        out["gw"], out["gx"] = gw, gx
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_run(orc, circ, w, x, batch, g=None):
+    W = circ.n_qubits
+    w64 = np.asarray(w, dtype=np.float64)
+    x64 = np.asarray(x, dtype=np.float64)
+    if g is None:
+        st = orc.forward(W, circ.gates, w64, x64, batch)
+        return {"state": st, "E": orc.expval(W, st)}
+    gw, gx, st = orc.adjoint(W, circ.gates, w64, x64, batch, g, want_state=True)
+    return {"state": st, "E": orc.expval(W, st), "gw": gw, "gx": gx}

@@ -1,0 +1,182 @@
+"""Host-side tests of libqsv (no GPU): exported symbols, argument validation,
+and the planner's split / schedule invariants checked with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_09213_amd import binding as B
+from paper_2404_09213_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2404_09213_amd import build_lib
+        build_lib.build()
+    return B.lib()
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "qsv.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsv_\w+)\s*\(", txt)))
+
+
+def test_exports_every_declared_function(lib):
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def _plan_rc(W, gates, n_w=4, n_in=2, opts=None):
+    arr = (B.qsv_gate * max(len(gates), 1))(*[B.qsv_gate(*g) for g in gates])
+    h = ctypes.c_void_p()
+    rc = B.lib().qsv_plan(W, arr, len(gates), n_w, n_in, ctypes.byref(opts) if opts else None,
+                          ctypes.byref(h))
+    if rc == 0:
+        B.qsv_plan_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("W,gate,code", [
+    (3, (11, 0, -1, 0, -1), -3),          # unknown kind
+    (3, (-1, 0, -1, 0, -1), -3),
+    (3, (0, 3, -1, 0, -1), -2),           # qubit >= W
+    (3, (0, -1, -1, 0, -1), -2),
+    (3, (7, 1, 1, 0, -1), -2),            # CNOT on one qubit
+    (3, (8, 0, 5, 0, -1), -2),            # CZ target out of range
+    (3, (4, 0, -1, 1, 4), -4),            # weight index out of range
+    (3, (4, 0, -1, 2, 2), -4),            # input column out of range
+    (3, (4, 0, -1, 0, -1), -4),           # rotation without an angle source
+    (3, (0, 0, -1, 1, 0), -4),            # fixed gate with an angle source
+    (31, (0, 0, -1, 0, -1), -5),          # W above the limit
+    (0, (0, 0, -1, 0, -1), -1),
+])
+def test_plan_rejects(lib, W, gate, code):
+    assert _plan_rc(W, [gate]) == code
+    assert B.qsv_last_error()
+
+
+def test_plan_rejects_bad_options(lib):
+    for field, val in [("fuse_width", 0), ("fuse_width", 17), ("tile_qubits", 3),
+                       ("tile_qubits", 13), ("low_qubits", 12), ("method", 2),
+                       ("max_pass_grads", 0)]:
+        o = B.qsv_default_opts()
+        setattr(o, field, val)
+        assert _plan_rc(4, [(0, 0, -1, 0, -1)], opts=o) == -1, field
+
+
+def test_calls_validate_before_touching_the_device(lib):
+    c = I.rx_ry_rz_cz_ladder(5, 1)
+    h = B.qsv_plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs)
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    big = 1 << 30
+    # batch <= 0
+    assert L.qsv_forward(h, fake, fake, 0, fake, fake, big, None) == -1
+    # missing workspace / too small
+    assert L.qsv_forward(h, fake, fake, 2, fake, None, 0, None) == -1
+    assert L.qsv_forward(h, fake, fake, 2, fake, fake, 8, None) == -1
+    assert L.qsv_expval(h, fake, 2, fake, fake, 8, None) == -1
+    assert L.qsv_backward(h, fake, fake, 2, fake, fake, fake, 8, fake, fake, None) == -1
+    # null pointers
+    assert L.qsv_forward(h, None, fake, 2, fake, fake, big, None) == -1
+    assert L.qsv_backward(h, fake, fake, 2, None, fake, fake, big, fake, fake, None) == -1
+    # null plan
+    assert L.qsv_forward(None, fake, fake, 2, fake, fake, big, None) == -8
+    assert L.qsv_workspace_size(None, 2, 0) == 0
+    info = B.qsv_plan_info()
+    assert L.qsv_plan_get_info(None, ctypes.byref(info)) == -8
+    B.qsv_plan_destroy(h)
+
+
+def test_strerror(lib):
+    for code in range(-8, 1):
+        assert B.qsv_strerror(code)
+
+
+def test_workspace_sizes_grow_with_batch(lib):
+    c = I.rx_ry_rz_cz_ladder(10, 2)
+    for method in ("fused", "per_gate"):
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method=method)
+        for op in (0, 1, 2):
+            s1 = B.qsv_workspace_size(p.handle, 1, op)
+            s8 = B.qsv_workspace_size(p.handle, 8, op)
+            assert 0 < s1 <= s8
+        # backward holds psi and lambda copies
+        assert B.qsv_workspace_size(p.handle, 8, 2) >= 2 * 8 * (1 << 10) * 8
+
+
+# -- planner invariants ----------------------------------------------------------------
+
+def _qubits(g):
+    return {g[1]} | ({g[2]} if g[0] in ("CNOT", "CZ", "CRX") else set())
+
+
+def _circuits():
+    rng = np.random.default_rng(5)
+    out = [I.rx_ry_rz_cz_ladder(12, 3), I.ry_rz_cnot_ring(9, 3), I.random_layers(10, 6, rng),
+           I.random_mixed(8, 150, rng, n_inputs=3, p_input=0.2), I.random_mixed(3, 60, rng),
+           I.random_mixed(6, 80, rng)]
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 6])
+def test_splitter_invariants(lib, k):
+    for c in _circuits():
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, fuse_width=k)
+        blk = p.gate_blocks()
+        assert np.all(blk >= 0)
+        nb = blk.max() + 1
+        assert p.info()["n_blocks"] == nb
+        # block qubit sets within k (a single gate may exceed k = 1)
+        for b in range(nb):
+            members = [c.gates[i] for i in np.nonzero(blk == b)[0]]
+            Q = set().union(*[_qubits(g) for g in members])
+            assert len(Q) <= k or len(members) == 1, (b, Q)
+        # per-qubit program order is preserved by executing blocks in index order
+        for q in range(c.n_qubits):
+            seq = [blk[i] for i, g in enumerate(c.gates) if q in _qubits(g)]
+            assert seq == sorted(seq)
+
+
+def test_splitter_block_counts_ladder(lib):
+    # 20-qubit RX/RY/RZ + CZ-ladder ansatz, 10 layers: blocks at k = 4, 5, 6
+    c = I.rx_ry_rz_cz_ladder(20, 10)
+    counts = [B.Plan(20, c.gates, c.n_weights, c.n_inputs, fuse_width=k).info()["n_blocks"]
+              for k in (4, 5, 6)]
+    assert counts == [68, 48, 40]
+
+
+@pytest.mark.parametrize("method", ["fused", "per_gate"])
+@pytest.mark.parametrize("k,m,cq", [(5, 12, 5), (3, 8, 2), (2, 6, 0), (6, 10, 4), (4, 4, 1)])
+def test_schedule_orders_are_valid(orc, lib, method, k, m, cq):
+    # Applying the gates in the order the kernels use must give the same state.
+    for c in _circuits():
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method=method, fuse_width=k,
+                   tile_qubits=m, low_qubits=cq)
+        w, x = I.draw_angles(c, 2, 3)
+        ref = orc.forward(c.n_qubits, c.gates, w.astype(np.float64), x.astype(np.float64), 2)
+        for which in (0, 1):
+            order = p.gate_order(which)
+            assert sorted(order.tolist()) == list(range(len(c.gates)))
+            if which == 1:
+                order = order[::-1]
+            gates = [c.gates[i] for i in order]
+            got = orc.forward(c.n_qubits, gates, w.astype(np.float64), x.astype(np.float64), 2)
+            assert np.max(np.abs(got - ref)) < 1e-12, (c.name, which)
+
+
+def test_prefix_covers_embedding_and_first_layer(lib):
+    c = I.rx_ry_rz_cz_ladder(20, 10)
+    info = B.Plan(20, c.gates, c.n_weights, c.n_inputs).info()
+    assert info["n_prefix_gates"] == 20 + 60
+    c2 = I.ry_rz_cnot_ring(16, 8)
+    assert B.Plan(16, c2.gates, c2.n_weights, c2.n_inputs).info()["n_prefix_gates"] == 16 + 32

@@ -1,0 +1,159 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Amplitudes and <Z_i> within 1e-5 max-abs; gradients within 1e-4 relative
+(normwise and per entry with a floor, see helpers.grad_close). Both methods
+(fused tiles and the plain per-gate method) and several tile shapes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2404_09213_amd import inputs as I
+
+from .helpers import AMP_TOL, EXP_TOL, grad_close, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+METHODS = ["fused", "per_gate"]
+
+
+def _check(circ, batch, seed, orc, method, grads=True, **opts):
+    w, x = I.draw_angles(circ, batch, seed)
+    g = I.draw_grad_out(circ, batch, seed) if grads else None
+    print(f"[parity] {circ.name} B={batch} seed={seed} method={method} opts={opts}", flush=True)
+    got = gpu_run(circ, w, x, batch, g, method=method, **opts)
+    ref = oracle_run(orc, circ, w, x, batch, g)
+    amp = np.abs(got["state"].cpu().numpy() - ref["state"]).max()
+    e = np.abs(got["E"].cpu().numpy() - ref["E"]).max()
+    assert amp <= AMP_TOL, amp
+    assert e <= EXP_TOL, e
+    if grads:
+        ok, rel = grad_close(got["gw"].cpu().numpy(), ref["gw"])
+        assert ok, ("weights", rel)
+        if circ.n_inputs:
+            ok, rel = grad_close(got["gx"].cpu().numpy(), ref["gx"])
+            assert ok, ("inputs", rel)
+    return got, ref
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_bell_and_ghz(orc, method):
+    for W in (2, 3, 6, 13):
+        c = I.Circuit(W, name=f"ghz{W}")
+        c.fixed("H", 0)
+        for q in range(W - 1):
+            c.fixed("CNOT", q, q + 1)
+        got = gpu_run(c, np.zeros(0, np.float32), np.zeros((1, 0), np.float32), 1, method=method)
+        st = got["state"].cpu().numpy()[0]
+        r = 1 / math.sqrt(2)
+        assert abs(st[0] - r) < 1e-6 and abs(st[-1] - r) < 1e-6
+        assert np.abs(st[1:-1]).max() < 1e-7
+        assert np.abs(got["E"].cpu().numpy()).max() < 1e-6
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_small_workload_w6_b8(orc, method):
+    c, batch, seed = I.workload("w6_b8_ring")
+    _check(c, batch, seed, orc, method)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("W,ng,seed", [(1, 20, 1), (2, 40, 2), (3, 60, 3), (4, 80, 4), (5, 90, 5),
+                                       (7, 120, 6), (9, 150, 7), (11, 150, 8), (13, 120, 9)])
+def test_random_mixed(orc, method, W, ng, seed):
+    rng = np.random.default_rng(seed)
+    c = I.random_mixed(W, ng, rng, n_inputs=3, p_input=0.2)
+    _check(c, 3, seed, orc, method)
+
+
+@pytest.mark.parametrize("k,m,cq", [(2, 4, 0), (3, 5, 1), (4, 6, 2), (5, 8, 3), (6, 9, 4),
+                                    (5, 10, 5), (3, 11, 6), (5, 12, 5), (1, 12, 11), (16, 12, 0)])
+def test_fused_tile_shapes(orc, k, m, cq):
+    rng = np.random.default_rng(100 + m)
+    c = I.random_mixed(13, 160, rng, n_inputs=4, p_input=0.2)
+    _check(c, 2, 100 + m, orc, "fused", fuse_width=k, tile_qubits=m, low_qubits=cq)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_ladder_and_ring_small(orc, method):
+    _check(I.rx_ry_rz_cz_ladder(14, 4), 3, 1003, orc, method)
+    _check(I.ry_rz_cnot_ring(13, 4), 3, 1002, orc, method)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_random_layers(orc, method):
+    rng = np.random.default_rng(1004)
+    for _ in range(3):
+        n = int(rng.integers(8, 15))
+        L = int(rng.integers(2, 13))
+        c = I.random_layers(n, L, rng)
+        _check(c, 1, 1004, orc, method)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_product_state_closed_form_w20(method):
+    # Ladder ansatz without entanglers: <Z_i> = cos(x_i + a_i) cos(theta_i) ... composed per
+    # layer; with one layer the closed form is exact at any size.
+    W = 20
+    c = I.rx_ry_rz_cz_ladder(W, 1)
+    c.gates = [g for g in c.gates if g[0] != "CZ"]
+    w, x = I.draw_angles(c, 4, 77)
+    got = gpu_run(c, w, x, 4, np.ones((4, W)), method=method)
+    w64, x64 = w.astype(np.float64), x.astype(np.float64)
+    a = w64.reshape(W, 3)[:, 0][None, :]
+    th = w64.reshape(W, 3)[:, 1][None, :]
+    E = np.cos(x64 + a) * np.cos(th)
+    assert np.abs(got["E"].cpu().numpy() - E).max() < EXP_TOL
+    gx = -np.sin(x64 + a) * np.cos(th)
+    ok, rel = grad_close(got["gx"].cpu().numpy(), gx)
+    assert ok, rel
+    gw = np.stack([(-np.sin(x64 + a) * np.cos(th)).sum(0), (-np.cos(x64 + a) * np.sin(th)).sum(0),
+                   np.zeros(W)], axis=1).reshape(-1)
+    assert np.abs(got["gw"].cpu().numpy() - gw).max() < 1e-4 * np.abs(gw).max()
+
+
+def _sampled_full_size(orc, name, method, samples):
+    """Full-size workload in the benchmark's launch configuration; the oracle
+    recomputes selected samples one by one. Weight gradients are linear in the
+    upstream gradient g, so zeroing g outside the selected samples makes the
+    GPU's batch-summed weight gradient comparable with the oracle's."""
+    c, batch, seed = I.workload(name)
+    w, x = I.draw_angles(c, batch, seed)
+    g = np.zeros((batch, c.n_qubits))
+    g[samples] = I.draw_grad_out(c, batch, seed)[samples]
+    print(f"[parity] {name} sampled {samples} method={method}", flush=True)
+    got = gpu_run(c, w, x, batch, g, method=method)
+    ref = oracle_run(orc, c, w, x[samples], len(samples), g[samples])
+    st = got["state"].cpu().numpy()[samples]
+    assert np.abs(st - ref["state"]).max() <= AMP_TOL
+    assert np.abs(got["E"].cpu().numpy()[samples] - ref["E"]).max() <= EXP_TOL
+    ok, rel = grad_close(got["gw"].cpu().numpy(), ref["gw"])
+    assert ok, ("weights", rel)
+    ok, rel = grad_close(got["gx"].cpu().numpy()[samples], ref["gx"])
+    assert ok, ("inputs", rel)
+    # samples with g = 0 have zero input gradients
+    others = [b for b in range(batch) if b not in samples]
+    assert np.abs(got["gx"].cpu().numpy()[others]).max() == 0.0
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_full_size_w20_b64_sampled(orc, method):
+    _sampled_full_size(orc, "w20_b64_ladder", method, [0, 37, 63])
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_full_size_w16_b256_sampled(orc, method):
+    _sampled_full_size(orc, "w16_b256_ring", method, [0, 101, 255])
+
+
+def test_fused_equals_per_gate_bitwise_deterministic(orc):
+    # Two runs of the same plan give identical bits (no atomics on result paths).
+    c = I.rx_ry_rz_cz_ladder(16, 3)
+    w, x = I.draw_angles(c, 4, 5)
+    g = I.draw_grad_out(c, 4, 5)
+    a = gpu_run(c, w, x, 4, g)
+    b = gpu_run(c, w, x, 4, g)
+    assert np.array_equal(a["state"].cpu().numpy(), b["state"].cpu().numpy())
+    assert np.array_equal(a["gw"].cpu().numpy(), b["gw"].cpu().numpy())
+    assert np.array_equal(a["gx"].cpu().numpy(), b["gx"].cpu().numpy())
