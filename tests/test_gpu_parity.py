@@ -8,6 +8,7 @@ import math
 
 import numpy as np
 import pytest
+import torch  # noqa: F401  (import once at collection, outside per-test time limits)
 
 from paper_2404_09213_amd import inputs as I
 
