@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + readout + adjoint backward of a parameterised circuit.
+
+One step = one pass of the whole hot path over one batch: gate-matrix cache
+evaluation, product-state init (angle embedding), every gate of the circuit,
+<Z_i> readout, and the adjoint backward giving all weight and input
+gradients of L = sum_{b,i} <Z_i>_b. Inputs for every step are generated
+beforehand and resident in HBM; each step draws fresh inputs and perturbed
+weights (as an optimizer step would), so nothing can be cached across steps.
+
+Default workload: 20 qubits, batch 64, embedding + 10 layers of
+[RX, RY, RZ on every qubit; CZ ladder], complex64, fused method. The plain
+per-gate method is timed beside it on the same inputs, and the CPU oracle is
+timed on a bounded sample.
+
+Prints one JSON line (rank 0, single GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector, TFLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=15)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="w20_b64_ladder")
+    ap.add_argument("--per-gate-steps", type=int, default=3)
+    ap.add_argument("--cpu-samples", type=int, default=4,
+                    help="batch samples the oracle is timed on (0 = skip)")
+    ap.add_argument("--fuse-width", type=int, default=None)
+    ap.add_argument("--tile-qubits", type=int, default=None)
+    ap.add_argument("--low-qubits", type=int, default=None)
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
+    """Warm up, then time `steps` steps; returns (ms_per_step, per-kernel stats, all ms)."""
+    B = state.shape[0]
+    n = len(ws_inputs)
+
+    def step(r):
+        w, x = ws_inputs[r % n]
+        plan.forward(w, x, B, state)
+        plan.expval(state, E)
+        plan.backward(w, x, state, g, gw=gw, gx=gx)
+
+    for r in range(warmup):
+        step(r)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()  # drop anything recorded before the timed region
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for r in range(warmup, warmup + steps):
+        step(r)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    stats = plan.profile_read()
+    plan.profile(False)
+    return total_ms / steps, stats
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2404_09213_amd import binding, inputs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    circ, B, seed = inputs.workload(args.workload)
+    W = circ.n_qubits
+    opts = {k: v for k, v in (("fuse_width", args.fuse_width), ("tile_qubits", args.tile_qubits),
+                              ("low_qubits", args.low_qubits)) if v is not None}
+    t_plan = time.perf_counter()
+    fused = binding.Plan(W, circ.gates, circ.n_weights, circ.n_inputs, method="fused", **opts)
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
+    per_gate = binding.Plan(W, circ.gates, circ.n_weights, circ.n_inputs, method="per_gate")
+    info = fused.info()
+    log(args, f"[bench] {args.workload}: W={W} B={B} gates={len(circ.gates)} plan={info}")
+
+    # inputs for every step, resident on the device before timing
+    n_runs = args.warmup + args.steps
+    runs = []
+    for r in range(n_runs):
+        w, x = inputs.draw_angles(circ, B, seed, run=r + 1)
+        runs.append((torch.from_numpy(w).to(dev), torch.from_numpy(x).to(dev)))
+    g = torch.ones((B, W), dtype=torch.float64, device=dev)   # L = sum_{b,i} <Z_i>
+    state = torch.empty((B, 1 << W), dtype=torch.complex64, device=dev)
+    E = torch.empty((B, W), dtype=torch.float64, device=dev)
+    gw = torch.empty((max(circ.n_weights, 1),), dtype=torch.float64, device=dev)
+    gx = torch.empty((B, max(circ.n_inputs, 1)), dtype=torch.float64, device=dev)
+
+    ms, stats = run_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch)
+    log(args, f"[bench] fused: {ms:.3f} ms/step")
+    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log(args, f"   {k:16s} launches={v['launches']:6d} ms={v['total_ms']:9.3f} "
+                  f"GB/s={v['bytes'] / max(v['total_ms'], 1e-9) / 1e6:8.1f} "
+                  f"TF/s={v['flops'] / max(v['total_ms'], 1e-9) / 1e9:7.2f}")
+
+    # parity spot check of the last timed step (sample 0) against the oracle
+    check = None
+    if args.cpu_samples > 0:
+        from oracle import oracle as orc
+        w_last, x_last = runs[(args.warmup + args.steps - 1) % n_runs]
+        w64 = w_last.cpu().numpy().astype(np.float64)
+        x64 = x_last.cpu().numpy().astype(np.float64)
+        ref_E = orc.expval(W, orc.forward(W, circ.gates, w64, x64[:1], 1))
+        check = {"sample": 0, "expval_max_abs_err": float(np.abs(E[:1].cpu().numpy() - ref_E).max())}
+
+    # plain per-gate method on the same inputs
+    pg = None
+    if args.per_gate_steps > 0:
+        pms, pstats = run_steps(per_gate, runs, g, state, E, gw, gx, args.per_gate_steps, 1, torch)
+        pbytes = sum(v["bytes"] for v in pstats.values()) / args.per_gate_steps
+        pg = {"ms_per_step": round(pms, 3), "evals_per_s": round(B / (pms / 1e3), 2),
+              "hbm_gbs": round(pbytes / (pms / 1e3) / 1e9, 1),
+              "hbm_frac": round(pbytes / (pms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+              "launches_per_step": int(sum(v["launches"] for v in pstats.values()) // args.per_gate_steps)}
+        log(args, f"[bench] per-gate: {pms:.3f} ms/step  {pg}")
+
+    # roofline of the dominant kernel (largest share of the timed region)
+    dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
+    gbs = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
+    tfs = dom["flops"] / (dom["total_ms"] / 1e3) / 1e12
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP32_VECTOR_PEAK_TF
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfs, 3), "peak": FP32_VECTOR_PEAK_TF,
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+    roof.update({"kernel": dom_name, "launches": dom["launches"],
+                 "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
+                 "alg_bytes_per_launch": dom["bytes"] / dom["launches"],
+                 "alg_flops_per_launch": dom["flops"] / dom["launches"],
+                 "hbm_frac": round(hbm_frac, 4), "alu_frac": round(alu_frac, 4),
+                 "traffic": None})
+
+    # CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if args.cpu_samples > 0:
+        from oracle import oracle as orc
+        ns = min(args.cpu_samples, B)
+        w0, x0 = runs[0]
+        w64 = w0.cpu().numpy().astype(np.float64)
+        x64 = x0.cpu().numpy()[:ns].astype(np.float64)
+        threads = len(os.sched_getaffinity(0))
+        t = time.perf_counter()
+        orc.adjoint(W, circ.gates, w64, x64, ns, np.ones((ns, W)))
+        dt = time.perf_counter() - t
+        cpu = {"value": round(ns / dt, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} of {B} samples of the same workload, complex128 forward + adjoint, "
+                         f"OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')}",
+               "seconds": round(dt, 2)}
+        log(args, f"[bench] cpu oracle: {cpu}")
+
+    out = {
+        "metric": "fwd+adjoint circuit evals/s & HBM GB/s, fused vs per-gate, 20q batch 64",
+        "value": round(B / (ms / 1e3), 2),
+        "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic: seeded inputs x~U(-pi,pi), weights~U(0,2pi), fresh per step",
+        "config": {"workload": args.workload, "n_qubits": W, "batch": B,
+                   "n_gates": len(circ.gates), "n_weights": circ.n_weights,
+                   "method": "fused", "fuse_width": info["fuse_width"],
+                   "tile_qubits": info["tile_qubits"], "low_qubits": info["low_qubits"],
+                   "fwd_passes": info["n_fwd_passes"], "bwd_passes": info["n_bwd_passes"],
+                   "plan_ms": round(plan_ms, 2)},
+        "per_gate": pg,
+        "speedup_fused_vs_per_gate": round(pg["ms_per_step"] / ms, 2) if pg else None,
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                        "gbs": round(v["bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
+                    for k, v in stats.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "check": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,29 @@ int qsv_plan_gate_order(const qsv_plan_t* plan, int32_t which, int32_t* order);
 /* Splitter block of every gate (blocks numbered in execution order). */
 int qsv_plan_gate_blocks(const qsv_plan_t* plan, int32_t* block_of_gate);
 
+/*
+ * Kernel profiling. While enabled, every kernel launch made by qsv_forward,
+ * qsv_expval and qsv_backward with this plan is bracketed by two HIP events
+ * recorded on the call's stream, and the launch's algorithmic traffic and
+ * arithmetic are noted:
+ *   bytes = 8 bytes per amplitude read or written (complex64) by the
+ *           method's definition of the step, not by the cache hierarchy;
+ *   flops = float32 operations of the gate arithmetic (complex multiply = 6).
+ * qsv_profile_read waits for the recorded events, writes up to max_out
+ * per-kernel totals, sets *n_out, and clears the record. Enabling or reading
+ * while another thread calls into the same plan is not supported.
+ */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;  /* sum of event-measured launch durations */
+    double bytes;     /* sum of algorithmic bytes */
+    double flops;     /* sum of algorithmic float32 operations */
+} qsv_kernel_stat;
+
+int qsv_profile_enable(qsv_plan_t* plan, int32_t on);
+int qsv_profile_read(qsv_plan_t* plan, qsv_kernel_stat* out, int32_t max_out, int32_t* n_out);
+
 const char* qsv_strerror(int code);
 const char* qsv_last_error(void);
 

@@ -53,9 +53,16 @@ class qsv_plan_info(ctypes.Structure):
         "n_fwd_stages", "n_bwd_stages", "n_param_gates", "n_recipes")]
 
 
+class qsv_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
 EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
-           "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_strerror", "qsv_last_error")
+           "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_profile_enable",
+           "qsv_profile_read", "qsv_strerror", "qsv_last_error")
 
 _lib = None
 
@@ -89,6 +96,11 @@ def lib():
         L.qsv_plan_gate_order.restype = ctypes.c_int
         L.qsv_plan_gate_blocks.argtypes = [vp, vp]
         L.qsv_plan_gate_blocks.restype = ctypes.c_int
+        L.qsv_profile_enable.argtypes = [vp, i32]
+        L.qsv_profile_enable.restype = ctypes.c_int
+        L.qsv_profile_read.argtypes = [vp, ctypes.POINTER(qsv_kernel_stat), i32,
+                                       ctypes.POINTER(i32)]
+        L.qsv_profile_read.restype = ctypes.c_int
         L.qsv_strerror.argtypes = [ctypes.c_int]
         L.qsv_strerror.restype = ctypes.c_char_p
         L.qsv_last_error.argtypes = []
@@ -165,6 +177,20 @@ def qsv_plan_gate_blocks(h, n_gates):
     return out[:n_gates]
 
 
+def qsv_profile_enable(h, on):
+    return _check(lib().qsv_profile_enable(h, int(bool(on))))
+
+
+def qsv_profile_read(h, max_out=32):
+    """Per-kernel totals since the last read: {name: {launches, total_ms, bytes, flops}}."""
+    arr = (qsv_kernel_stat * max_out)()
+    n = ctypes.c_int32()
+    _check(lib().qsv_profile_read(h, arr, max_out, ctypes.byref(n)))
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                   "bytes": arr[i].bytes, "flops": arr[i].flops}
+            for i in range(n.value)}
+
+
 def qsv_strerror(code):
     return lib().qsv_strerror(int(code)).decode()
 
@@ -216,6 +242,12 @@ class Plan:
 
     def gate_blocks(self):
         return qsv_plan_gate_blocks(self.handle, self.n_gates)
+
+    def profile(self, on=True):
+        qsv_profile_enable(self.handle, on)
+
+    def profile_read(self):
+        return qsv_profile_read(self.handle)
 
     def workspace(self, batch, op, device):
         import torch

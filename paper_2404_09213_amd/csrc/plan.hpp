@@ -167,6 +167,12 @@ struct qsv_plan_s {
     std::vector<int32_t> fwd_order, bwd_order;
     int n_fwd_stages = 0, n_bwd_stages = 0;
 
+    // algorithmic float32 operations per amplitude of each launch (profiling)
+    std::vector<double> fwd_pass_flops, bwd_pass_flops, pg_fwd_flops, pg_bwd_flops;
+
+    // profiling state (opaque; owned by the HIP side)
+    mutable void* prof = nullptr;
+
     // lazily created device copies, per device ordinal
     mutable std::mutex dev_mu;
     mutable std::map<int, qsv::DeviceTables> dev;

@@ -416,6 +416,43 @@ struct PassBuilder {
     }
 };
 
+// Float32 operations per amplitude of one op (complex multiply = 6, add = 2).
+double op_flops(const DOp& o) {
+    const double half = o.ctl >= 0 ? 0.5 : 1.0;
+    switch (o.kind) {
+    case OP_U2: return 14.0 * half;    // two complex products and a sum per output
+    case OP_REAL: case OP_RXL: return 6.0 * half;
+    case OP_DIAG: return 6.0;
+    case OP_GX: case OP_GY: return 3.5 * half;
+    case OP_GZ: return 4.0;
+    default: return 0.0;               // sign flips and swaps move data only
+    }
+}
+
+double pass_flops(const qsv_plan_t* p, const DPass& ps, bool backward) {
+    double f = 0.0;
+    for (int s = ps.stage0; s < ps.stage0 + ps.n_stages; ++s)
+        for (int o = p->stages[s].op0; o < p->stages[s].op1; ++o) {
+            const DOp& op = p->ops[o];
+            const bool grad = op.kind >= OP_GX;
+            f += op_flops(op) * (backward && !grad ? 2.0 : 1.0);
+        }
+    return f;
+}
+
+double pg_flops(const PGate& g, bool backward) {
+    DOp o;
+    std::memset(&o, 0, sizeof o);
+    o.kind = g.cls;
+    o.ctl = g.csh >= 0 ? 0 : -1;
+    double f = op_flops(o) * (backward ? 2.0 : 1.0);
+    if (backward && g.grad >= 0) {
+        o.kind = g.grad;
+        f += op_flops(o);
+    }
+    return f;
+}
+
 int pg_class(const qsv_plan_t* p, int g) {
     const int k = p->gates[g].kind;
     if (k == QSV_CZ) return OP_SIGN;
@@ -518,6 +555,8 @@ int build_plan(qsv_plan_t* p) {
             p->pg_bwd.push_back(x);
             p->bwd_order.push_back(g);
         }
+        for (auto& x : p->pg_fwd) p->pg_fwd_flops.push_back(pg_flops(x, false));
+        for (auto& x : p->pg_bwd) p->pg_bwd_flops.push_back(pg_flops(x, true));
         return QSV_OK;
     }
 
@@ -548,8 +587,14 @@ int build_plan(qsv_plan_t* p) {
             pb.build(passes[i], dense[i], m, c, flags, p->bwd_pass, p->bwd_order);
         }
     }
-    for (auto& ps : p->fwd_pass) p->n_fwd_stages += ps.n_stages;
-    for (auto& ps : p->bwd_pass) p->n_bwd_stages += ps.n_stages;
+    for (auto& ps : p->fwd_pass) {
+        p->n_fwd_stages += ps.n_stages;
+        p->fwd_pass_flops.push_back(pass_flops(p, ps, false));
+    }
+    for (auto& ps : p->bwd_pass) {
+        p->n_bwd_stages += ps.n_stages;
+        p->bwd_pass_flops.push_back(pass_flops(p, ps, true));
+    }
     return QSV_OK;
 }
 

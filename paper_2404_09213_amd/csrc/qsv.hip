@@ -912,6 +912,51 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
 // ----------------------------------------------------------------------------
 namespace {
 
+// ---- profiling: event pairs around launches, per-kernel totals ----
+enum KernelId { K_COEF, K_INIT, K_PASS_FWD, K_PASS_BWD, K_PG_APPLY, K_PG_ADJ, K_ADJ_INIT,
+                K_EXPVAL_PART, K_EXPVAL_FINAL, K_GRAD_REDUCE, K_COUNT };
+const char* const kKernelNames[K_COUNT] = {"k_coef", "k_init", "k_pass_fwd", "k_pass_bwd",
+                                           "k_pg_apply", "k_pg_adj", "k_adj_init",
+                                           "k_expval_part", "k_expval_final", "k_grad_reduce"};
+
+struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+struct Profiler {
+    bool on = false;
+    std::mutex mu;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+Profiler* prof_of(const qsv_plan_t* p) { return static_cast<Profiler*>(p->prof); }
+
+// Returns the start event (or nullptr when profiling is off).
+hipEvent_t prof_begin(const qsv_plan_t* p, hipStream_t s) {
+    Profiler* pr = prof_of(p);
+    if (!pr || !pr->on) return nullptr;
+    std::lock_guard<std::mutex> lk(pr->mu);
+    hipEvent_t e = nullptr;
+    if (!pr->pool.empty()) { e = pr->pool.back(); pr->pool.pop_back(); }
+    else if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    (void)hipEventRecord(e, s);
+    return e;
+}
+
+void prof_end(const qsv_plan_t* p, hipStream_t s, hipEvent_t a, int kid, double bytes, double flops) {
+    if (!a) return;
+    Profiler* pr = prof_of(p);
+    std::lock_guard<std::mutex> lk(pr->mu);
+    hipEvent_t b = nullptr;
+    if (!pr->pool.empty()) { b = pr->pool.back(); pr->pool.pop_back(); }
+    else if (hipEventCreate(&b) != hipSuccess) { pr->pool.push_back(a); return; }
+    (void)hipEventRecord(b, s);
+    pr->recs.push_back({kid, a, b, bytes, flops});
+}
+
 template <class T>
 size_t bytes_of(const std::vector<T>& v) { return v.size() * sizeof(T); }
 
@@ -1008,8 +1053,10 @@ int run_coef(const qsv_plan_t* p, DeviceTables* T, const float* w, const float* 
     const int nr = (int)p->recipes.size();
     if (nr == 0) return QSV_OK;
     dim3 grid((nr + 127) / 128, (unsigned)(p->n_ps_mats ? B : 1));
+    hipEvent_t ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_coef, grid, dim3(128), 0, s, T->gates, T->recipes, T->recipe_gates, nr,
                        w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, mats);
+    prof_end(p, s, ev, K_COEF, 32.0 * ((double)p->n_shared_mats + (double)B * p->n_ps_mats), 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }
@@ -1018,8 +1065,11 @@ int run_init(const qsv_plan_t* p, DeviceTables* T, const float* mats, int64_t B,
              hipStream_t s) {
     const int cb = std::min(p->W, 12);
     dim3 grid((unsigned)(int64_t(1) << (p->W - cb)), (unsigned)B);
+    hipEvent_t ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_init, grid, dim3(256), 0, s, st, p->W, T->prefix_mat, mats,
                        p->n_shared_mats, p->n_ps_mats);
+    const double amps = (double)B * (double)(int64_t(1) << p->W);
+    prof_end(p, s, ev, K_INIT, 8.0 * amps, 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }
@@ -1152,6 +1202,11 @@ void qsv_plan_destroy(qsv_plan_t* p) {
         if (hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second.base);
     }
     if (have && !p->dev.empty()) (void)hipSetDevice(cur);
+    if (Profiler* pr = prof_of(p)) {
+        for (auto& r : pr->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pr->pool) (void)hipEventDestroy(e);
+        delete pr;
+    }
     delete p;
 }
 
@@ -1229,15 +1284,20 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
     if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
     if ((rc = run_init(p, T, mats, B, st, s))) return rc;
     const int W = p->W;
+    const double amps = (double)B * (double)(int64_t(1) << W);
     if (p->opts.method == QSV_METHOD_PER_GATE) {
-        for (const PGate& pg : p->pg_fwd) {
+        for (size_t i = 0; i < p->pg_fwd.size(); ++i) {
+            const PGate& pg = p->pg_fwd[i];
             int64_t items;
-            if (pg.cls == OP_DIAG) items = B << W;
-            else if (pg.cls == OP_SIGN) items = B << (W - 2);
-            else items = B << (W - 1 - (pg.csh >= 0 ? 1 : 0));
+            double touched;  // fraction of the amplitudes the gate changes
+            if (pg.cls == OP_DIAG) { items = B << W; touched = 1.0; }
+            else if (pg.cls == OP_SIGN) { items = B << (W - 2); touched = 0.25; }
+            else { items = B << (W - 1 - (pg.csh >= 0 ? 1 : 0)); touched = pg.csh >= 0 ? 0.5 : 1.0; }
             const int64_t blocks = (items + 256 * kPgItems - 1) / (256 * kPgItems);
+            hipEvent_t ev = prof_begin(p, s);
             hipLaunchKernelGGL(k_pg_apply, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
                                (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+            prof_end(p, s, ev, K_PG_APPLY, 16.0 * touched * amps, p->pg_fwd_flops[i] * amps);
         }
         HIP_TRY(hipGetLastError());
         return QSV_OK;
@@ -1247,9 +1307,11 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
     const unsigned tiles = (unsigned)(B << (W - m));
     const size_t lds = pass_lds_fwd(p);
     for (size_t i = 0; i < p->fwd_pass.size(); ++i) {
+        hipEvent_t ev = prof_begin(p, s);
         hipLaunchKernelGGL(k_pass_fwd, dim3(tiles), dim3(threads), lds, s, T->fwd_pass + i,
                            T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
                            p->n_ps_mats, st, W);
+        prof_end(p, s, ev, K_PASS_FWD, 16.0 * amps, p->fwd_pass_flops[i] * amps);
     }
     HIP_TRY(hipGetLastError());
     return QSV_OK;
@@ -1266,10 +1328,15 @@ int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out,
     hipStream_t s = (hipStream_t)stream;
     const int64_t nchunk = expval_nchunk(p);
     double* part = (double*)ws;
+    const double amps = (double)B * (double)(int64_t(1) << p->W);
+    hipEvent_t ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_expval_part, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
                        (const float2*)d_state, p->W, part);
+    prof_end(p, s, ev, K_EXPVAL_PART, 8.0 * amps, 3.0 * amps);
+    ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_expval_final, dim3((unsigned)p->W, (unsigned)B), dim3(256), 0, s,
                        (const double*)part, p->W, nchunk, out);
+    prof_end(p, s, ev, K_EXPVAL_FINAL, 8.0 * (double)B * nchunk * p->W, 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }
@@ -1300,14 +1367,21 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     double* part = (double*)c;
     if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
     const int64_t nch = grad_nch(p);
+    const double amps = (double)B * (double)(int64_t(1) << W);
     if (p->opts.method == QSV_METHOD_PER_GATE) {
         const int64_t n = B << W;
+        hipEvent_t ev = prof_begin(p, s);
         hipLaunchKernelGGL(k_adj_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                            (const float2*)d_state, psi, lam, W, B, gout);
-        for (const PGate& pg : p->pg_bwd) {
+        prof_end(p, s, ev, K_ADJ_INIT, 24.0 * amps, 2.0 * W * amps);
+        for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
+            const PGate& pg = p->pg_bwd[i];
+            const double touched = pg.cls == OP_SIGN ? 0.25 : (pg.csh >= 0 ? 0.5 : 1.0);
+            ev = prof_begin(p, s);
             hipLaunchKernelGGL(k_pg_adj, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi,
                                lam, W, (int)B, pg, (const float*)mats, p->n_shared_mats,
                                p->n_ps_mats, part, nch);
+            prof_end(p, s, ev, K_PG_ADJ, 32.0 * touched * amps, p->pg_bwd_flops[i] * amps);
         }
     } else {
         const int m = std::min(p->opts.tile_qubits, W);
@@ -1315,19 +1389,77 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
         const unsigned tiles = (unsigned)(B << (W - m));
         const size_t lds = pass_lds_bwd(p);
         for (size_t i = 0; i < p->bwd_pass.size(); ++i) {
+            const int fl = p->bwd_pass[i].flags;
+            // psi_N read (8) or psi, lambda read (16); psi, lambda written (16) unless last
+            const double per_amp = ((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0);
+            hipEvent_t ev = prof_begin(p, s);
             hipLaunchKernelGGL(k_pass_bwd, dim3(tiles), dim3(threads), lds, s, T->bwd_pass + i,
                                T->stages, T->ops, T->terms, T->gslot_map, (const float*)mats,
                                p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
                                gout, W, (int)B, part);
+            prof_end(p, s, ev, K_PASS_BWD, per_amp * amps, p->bwd_pass_flops[i] * amps);
         }
     }
     const int n_out = p->n_weights + (gx ? (int)B * p->n_inputs : 0);
-    if (n_out > 0)
+    if (n_out > 0) {
+        hipEvent_t ev = prof_begin(p, s);
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)n_out), dim3(256), 0, s,
                            (const double*)part, T->grad_csr, p->n_weights, p->n_inputs, (int)B, nch,
                            gw, gx);
+        prof_end(p, s, ev, K_GRAD_REDUCE, 8.0 * (double)std::max(p->n_param, 1) * B * nch, 0.0);
+    }
     HIP_TRY(hipGetLastError());
     return QSV_OK;
+}
+
+int qsv_profile_enable(qsv_plan_t* p, int32_t on) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!p->prof) {
+        Profiler* pr = new (std::nothrow) Profiler();
+        if (!pr) { set_error("profiler allocation failed"); return QSV_ERR_OOM; }
+        p->prof = pr;
+    }
+    prof_of(p)->on = on != 0;
+    return QSV_OK;
+}
+
+int qsv_profile_read(qsv_plan_t* p, qsv_kernel_stat* out, int32_t max_out, int32_t* n_out) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!n_out || (max_out > 0 && !out)) { set_error("null pointer"); return QSV_ERR_ARG; }
+    qsv_kernel_stat tot[K_COUNT];
+    std::memset(tot, 0, sizeof tot);
+    Profiler* pr = prof_of(p);
+    int err = QSV_OK;
+    if (pr) {
+        std::lock_guard<std::mutex> lk(pr->mu);
+        for (auto& r : pr->recs) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+                set_error("event timing failed");
+                err = QSV_ERR_HIP;
+            }
+            tot[r.kid].launches++;
+            tot[r.kid].total_ms += ms;
+            tot[r.kid].bytes += r.bytes;
+            tot[r.kid].flops += r.flops;
+            pr->pool.push_back(r.a);
+            pr->pool.push_back(r.b);
+        }
+        pr->recs.clear();
+    }
+    int n = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (!tot[k].launches) continue;
+        if (n < max_out) {
+            out[n] = tot[k];
+            std::snprintf(out[n].name, sizeof out[n].name, "%s", kKernelNames[k]);
+        }
+        ++n;
+    }
+    *n_out = std::min(n, max_out);
+    return err;
 }
 
 }  // extern "C"
