@@ -44,7 +44,30 @@ def parse():
     ap.add_argument("--tile-qubits", type=int, default=None)
     ap.add_argument("--low-qubits", type=int, default=None)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
+                    help="copy: time a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(args):
+    """A plain device-to-device copy of 1 GiB, three times: the reference for
+    scaling rocprofv3's FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = 1 << 28  # float32 elements = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "ms": [round(x, 4) for x in ms],
+                      "gbs": round(8 * n / (min(ms) / 1e3) / 1e9, 1)}), flush=True)
 
 
 def log(args, *a):
@@ -85,6 +108,9 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
 
 def main():
     args = parse()
+    if args.mode == "copy":
+        copy_calibration(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -102,7 +102,10 @@ typedef struct {
     int32_t low_qubits;  /* c: number of lowest-stride qubits every tile keeps
                             (contiguous runs of 2^c amplitudes); 0..m-1 */
     int32_t max_pass_grads; /* cap on parametric gates per backward pass, 1..256 */
-    int32_t reserved[3];
+    int32_t codegen;     /* fused method: 1 = kernels generated for this plan and
+                            compiled with hipRTC on first use on a device (default);
+                            0 = table-driven kernels compiled into the library */
+    int32_t reserved[2];
 } qsv_opts;
 
 typedef struct {
@@ -120,7 +123,7 @@ typedef struct {
 
 typedef struct qsv_plan_s qsv_plan_t;
 
-/* Fill *opts with the defaults (fused, k = 5, m = 12, c = 5, 256). */
+/* Fill *opts with the defaults (fused, k = 5, m = 12, c = 5, 256, codegen 1). */
 void qsv_default_opts(qsv_opts* opts);
 
 /*
@@ -188,6 +191,20 @@ int qsv_plan_gate_order(const qsv_plan_t* plan, int32_t which, int32_t* order);
 
 /* Splitter block of every gate (blocks numbered in execution order). */
 int qsv_plan_gate_blocks(const qsv_plan_t* plan, int32_t* block_of_gate);
+
+/*
+ * Generated source of a fused plan's pass kernels (codegen = 1). Copies at
+ * most buf_size bytes including the terminating NUL into buf (may be NULL)
+ * and stores the full size including the NUL in *needed.
+ */
+int qsv_plan_codegen_source(const qsv_plan_t* plan, char* buf, size_t buf_size, size_t* needed);
+
+/*
+ * Compile a fused plan's generated kernels with hipRTC for the named
+ * architecture (e.g. "gfx950") without touching any device; on failure the
+ * compiler log is available from qsv_last_error(). Host only.
+ */
+int qsv_plan_codegen_check(const qsv_plan_t* plan, const char* arch);
 
 /*
  * Kernel profiling. While enabled, every kernel launch made by qsv_forward,

@@ -43,7 +43,8 @@ class qsv_gate(ctypes.Structure):
 class qsv_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("fuse_width", ctypes.c_int32),
                 ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
-                ("max_pass_grads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -61,7 +62,8 @@ class qsv_kernel_stat(ctypes.Structure):
 
 EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
-           "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_profile_enable",
+           "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
+           "qsv_plan_codegen_check", "qsv_profile_enable",
            "qsv_profile_read", "qsv_strerror", "qsv_last_error")
 
 _lib = None
@@ -96,6 +98,10 @@ def lib():
         L.qsv_plan_gate_order.restype = ctypes.c_int
         L.qsv_plan_gate_blocks.argtypes = [vp, vp]
         L.qsv_plan_gate_blocks.restype = ctypes.c_int
+        L.qsv_plan_codegen_source.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+        L.qsv_plan_codegen_source.restype = ctypes.c_int
+        L.qsv_plan_codegen_check.argtypes = [vp, ctypes.c_char_p]
+        L.qsv_plan_codegen_check.restype = ctypes.c_int
         L.qsv_profile_enable.argtypes = [vp, i32]
         L.qsv_profile_enable.restype = ctypes.c_int
         L.qsv_profile_read.argtypes = [vp, ctypes.POINTER(qsv_kernel_stat), i32,
@@ -177,6 +183,18 @@ def qsv_plan_gate_blocks(h, n_gates):
     return out[:n_gates]
 
 
+def qsv_plan_codegen_source(h):
+    need = ctypes.c_size_t()
+    _check(lib().qsv_plan_codegen_source(h, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().qsv_plan_codegen_source(h, buf, need.value, ctypes.byref(need)))
+    return buf.value.decode()
+
+
+def qsv_plan_codegen_check(h, arch):
+    return _check(lib().qsv_plan_codegen_check(h, arch.encode()))
+
+
 def qsv_profile_enable(h, on):
     return _check(lib().qsv_profile_enable(h, int(bool(on))))
 
@@ -202,8 +220,10 @@ def qsv_last_error():
 # -- plan owner with torch-allocated workspaces -------------------------------------
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
-              max_pass_grads=None):
+              max_pass_grads=None, codegen=None):
     o = qsv_default_opts()
+    if codegen is not None:
+        o.codegen = int(codegen)
     o.method = METHOD[method] if isinstance(method, str) else int(method)
     if fuse_width is not None:
         o.fuse_width = fuse_width

@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = [os.path.join(HERE, "csrc", "qsv.hip"), os.path.join(HERE, "csrc", "planner.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", "qsv.hip"), os.path.join(HERE, "csrc", "planner.cpp"),
+           os.path.join(HERE, "csrc", "jit.cpp")]
 OUT = os.path.join(HERE, "libqsv.so")
 
 FLAGS = [
@@ -26,7 +27,7 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES, "-lhiprtc", "-pthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops"
     msgs = [l for l in (res.stdout + res.stderr).splitlines() if noise not in l and l.strip()]

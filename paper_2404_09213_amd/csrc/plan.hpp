@@ -123,6 +123,9 @@ struct DeviceTables {
     int32_t* gslot_map = nullptr;
     int32_t* prefix_mat = nullptr;
     int32_t* grad_csr = nullptr;   // weights then inputs: offsets, then slot lists
+    // generated pass kernels (hipModule_t / hipFunction_t, kept opaque here)
+    std::vector<void*> modules;
+    std::vector<void*> fwd_fn, bwd_fn;
 };
 
 }  // namespace qsv

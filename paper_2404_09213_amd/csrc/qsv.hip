@@ -19,6 +19,7 @@
 #include <new>
 #include <string>
 
+#include "jit.hpp"
 #include "plan.hpp"
 
 using namespace qsv;
@@ -1014,6 +1015,41 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     t.gslot_map = (int32_t*)(c + offs[8]);
     t.prefix_mat = (int32_t*)(c + offs[9]);
     t.grad_csr = (int32_t*)(c + offs[10]);
+    if (p->opts.method == QSV_METHOD_FUSED && p->opts.codegen &&
+        !(p->fwd_pass.empty() && p->bwd_pass.empty())) {
+        JitModules jm;
+        std::string err;
+        int rc = jit_compile(p, "", jm, err);
+        if (rc != QSV_OK) {
+            (void)hipFree(d);
+            set_error(err);
+            return rc;
+        }
+        std::vector<hipModule_t> mods(jm.codes.size());
+        for (size_t g = 0; g < jm.codes.size(); ++g) {
+            hipError_t le = hipModuleLoadData(&mods[g], jm.codes[g].data());
+            if (le != hipSuccess) {
+                for (size_t h = 0; h < g; ++h) (void)hipModuleUnload(mods[h]);
+                (void)hipFree(d);
+                set_error(std::string("hipModuleLoadData: ") + hipGetErrorString(le));
+                return QSV_ERR_HIP;
+            }
+            t.modules.push_back((void*)mods[g]);
+        }
+        t.fwd_fn.assign(p->fwd_pass.size(), nullptr);
+        t.bwd_fn.assign(p->bwd_pass.size(), nullptr);
+        for (const JitKernelRef& r : jm.refs) {
+            hipFunction_t f = nullptr;
+            hipError_t fe = hipModuleGetFunction(&f, mods[r.group], r.name.c_str());
+            if (fe != hipSuccess) {
+                for (auto m : mods) (void)hipModuleUnload(m);
+                (void)hipFree(d);
+                set_error("hipModuleGetFunction(" + r.name + "): " + hipGetErrorString(fe));
+                return QSV_ERR_HIP;
+            }
+            (r.which == 0 ? t.fwd_fn : t.bwd_fn)[r.pass] = (void*)f;
+        }
+    }
     auto res = p->dev.emplace(dev, t);
     *out = &res.first->second;
     return QSV_OK;
@@ -1126,6 +1162,7 @@ void qsv_default_opts(qsv_opts* o) {
     o->tile_qubits = 12;
     o->low_qubits = 5;
     o->max_pass_grads = 256;
+    o->codegen = 1;
 }
 
 int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n_weights,
@@ -1144,6 +1181,7 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.tile_qubits < kRegBits || o.tile_qubits > kMaxTileQubits) { set_error("tile_qubits must be in 4..12"); return QSV_ERR_ARG; }
     if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
+    if (o.codegen != 0 && o.codegen != 1) { set_error("codegen must be 0 or 1"); return QSV_ERR_ARG; }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
@@ -1199,7 +1237,10 @@ void qsv_plan_destroy(qsv_plan_t* p) {
     int cur = 0;
     const bool have = hipGetDevice(&cur) == hipSuccess;
     for (auto& kv : p->dev) {
-        if (hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second.base);
+        if (hipSetDevice(kv.first) == hipSuccess) {
+            for (void* m : kv.second.modules) (void)hipModuleUnload((hipModule_t)m);
+            (void)hipFree(kv.second.base);
+        }
     }
     if (have && !p->dev.empty()) (void)hipSetDevice(cur);
     if (Profiler* pr = prof_of(p)) {
@@ -1308,9 +1349,17 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
     const size_t lds = pass_lds_fwd(p);
     for (size_t i = 0; i < p->fwd_pass.size(); ++i) {
         hipEvent_t ev = prof_begin(p, s);
-        hipLaunchKernelGGL(k_pass_fwd, dim3(tiles), dim3(threads), lds, s, T->fwd_pass + i,
-                           T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
-                           p->n_ps_mats, st, W);
+        if (!T->fwd_fn.empty()) {
+            int ns = p->n_shared_mats, np = p->n_ps_mats;
+            const float* mp = mats;
+            void* args[] = {&st, &mp, &ns, &np};
+            HIP_TRY(hipModuleLaunchKernel((hipFunction_t)T->fwd_fn[i], tiles, 1, 1, threads, 1, 1, 0,
+                                          s, args, nullptr));
+        } else {
+            hipLaunchKernelGGL(k_pass_fwd, dim3(tiles), dim3(threads), lds, s, T->fwd_pass + i,
+                               T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
+                               p->n_ps_mats, st, W);
+        }
         prof_end(p, s, ev, K_PASS_FWD, 16.0 * amps, p->fwd_pass_flops[i] * amps);
     }
     HIP_TRY(hipGetLastError());
@@ -1393,10 +1442,19 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
             // psi_N read (8) or psi, lambda read (16); psi, lambda written (16) unless last
             const double per_amp = ((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0);
             hipEvent_t ev = prof_begin(p, s);
-            hipLaunchKernelGGL(k_pass_bwd, dim3(tiles), dim3(threads), lds, s, T->bwd_pass + i,
-                               T->stages, T->ops, T->terms, T->gslot_map, (const float*)mats,
-                               p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
-                               gout, W, (int)B, part);
+            if (!T->bwd_fn.empty()) {
+                const void* psiN = d_state;
+                const float* mp = mats;
+                int ns = p->n_shared_mats, np = p->n_ps_mats, bb = (int)B;
+                void* args[] = {&psiN, &psi, &lam, &gout, &mp, &ns, &np, &part, &bb};
+                HIP_TRY(hipModuleLaunchKernel((hipFunction_t)T->bwd_fn[i], tiles, 1, 1, threads, 1, 1, 0,
+                                              s, args, nullptr));
+            } else {
+                hipLaunchKernelGGL(k_pass_bwd, dim3(tiles), dim3(threads), lds, s, T->bwd_pass + i,
+                                   T->stages, T->ops, T->terms, T->gslot_map, (const float*)mats,
+                                   p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
+                                   gout, W, (int)B, part);
+            }
             prof_end(p, s, ev, K_PASS_BWD, per_amp * amps, p->bwd_pass_flops[i] * amps);
         }
     }
@@ -1410,6 +1468,33 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     }
     HIP_TRY(hipGetLastError());
     return QSV_OK;
+}
+
+int qsv_plan_codegen_source(const qsv_plan_t* p, char* buf, size_t buf_size, size_t* needed) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!needed) { set_error("needed is NULL"); return QSV_ERR_ARG; }
+    std::vector<JitKernelRef> refs;
+    const std::string src = p->opts.method == QSV_METHOD_FUSED ? jit_source(p, refs, 1 << 30) : std::string();
+    *needed = src.size() + 1;
+    if (buf && buf_size) {
+        const size_t n = std::min(buf_size - 1, src.size());
+        std::memcpy(buf, src.data(), n);
+        buf[n] = 0;
+    }
+    return QSV_OK;
+}
+
+int qsv_plan_codegen_check(const qsv_plan_t* p, const char* arch) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!arch || !*arch) { set_error("arch is empty"); return QSV_ERR_ARG; }
+    if (p->opts.method != QSV_METHOD_FUSED) return QSV_OK;
+    JitModules jm;
+    std::string err;
+    rc = jit_compile(p, arch, jm, err);
+    if (rc) set_error(err);
+    return rc;
 }
 
 int qsv_profile_enable(qsv_plan_t* p, int32_t on) {

@@ -66,7 +66,7 @@ def test_plan_rejects(lib, W, gate, code):
 
 def test_plan_rejects_bad_options(lib):
     for field, val in [("fuse_width", 0), ("fuse_width", 17), ("tile_qubits", 3),
-                       ("tile_qubits", 13), ("low_qubits", 12), ("method", 2),
+                       ("tile_qubits", 13), ("low_qubits", 12), ("method", 2), ("codegen", 2),
                        ("max_pass_grads", 0)]:
         o = B.qsv_default_opts()
         setattr(o, field, val)
@@ -180,3 +180,22 @@ def test_prefix_covers_embedding_and_first_layer(lib):
     assert info["n_prefix_gates"] == 20 + 60
     c2 = I.ry_rz_cnot_ring(16, 8)
     assert B.Plan(16, c2.gates, c2.n_weights, c2.n_inputs).info()["n_prefix_gates"] == 16 + 32
+
+
+@pytest.mark.slow
+def test_generated_kernels_compile_for_gfx950(lib):
+    # The per-plan kernels compile for gfx950 without a GPU (small plans).
+    rng = np.random.default_rng(12)
+    for c, opts in [(I.random_mixed(6, 40, rng, n_inputs=2, p_input=0.3), dict(tile_qubits=5, low_qubits=1)),
+                    (I.rx_ry_rz_cz_ladder(11, 2), dict(tile_qubits=10, low_qubits=4)),
+                    (I.random_layers(9, 3, rng), dict(tile_qubits=8, low_qubits=3))]:
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, **opts)
+        src = B.qsv_plan_codegen_source(p.handle)
+        assert src.count("__global__") == p.info()["n_fwd_passes"] + p.info()["n_bwd_passes"]
+        B.qsv_plan_codegen_check(p.handle, "gfx950")
+
+
+def test_codegen_source_empty_for_per_gate(lib):
+    c = I.rx_ry_rz_cz_ladder(6, 1)
+    p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="per_gate")
+    assert B.qsv_plan_codegen_source(p.handle) == ""

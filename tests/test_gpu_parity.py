@@ -16,14 +16,24 @@ from .helpers import AMP_TOL, EXP_TOL, grad_close, gpu_run, oracle_run
 
 pytestmark = pytest.mark.gpu
 
-METHODS = ["fused", "per_gate"]
+# fused = generated per-plan kernels; fused_tables = table-driven kernels; per_gate = plain method
+METHODS = ["fused", "fused_tables", "per_gate"]
+_METHOD_OPTS = {"fused": {"method": "fused", "codegen": 1},
+                "fused_tables": {"method": "fused", "codegen": 0},
+                "per_gate": {"method": "per_gate"}}
+
+
+def _opts(method, **extra):
+    o = dict(_METHOD_OPTS[method])
+    o.update(extra)
+    return o
 
 
 def _check(circ, batch, seed, orc, method, grads=True, **opts):
     w, x = I.draw_angles(circ, batch, seed)
     g = I.draw_grad_out(circ, batch, seed) if grads else None
     print(f"[parity] {circ.name} B={batch} seed={seed} method={method} opts={opts}", flush=True)
-    got = gpu_run(circ, w, x, batch, g, method=method, **opts)
+    got = gpu_run(circ, w, x, batch, g, **_opts(method, **opts))
     ref = oracle_run(orc, circ, w, x, batch, g)
     amp = np.abs(got["state"].cpu().numpy() - ref["state"]).max()
     e = np.abs(got["E"].cpu().numpy() - ref["E"]).max()
@@ -45,7 +55,7 @@ def test_bell_and_ghz(orc, method):
         c.fixed("H", 0)
         for q in range(W - 1):
             c.fixed("CNOT", q, q + 1)
-        got = gpu_run(c, np.zeros(0, np.float32), np.zeros((1, 0), np.float32), 1, method=method)
+        got = gpu_run(c, np.zeros(0, np.float32), np.zeros((1, 0), np.float32), 1, **_opts(method))
         st = got["state"].cpu().numpy()[0]
         r = 1 / math.sqrt(2)
         assert abs(st[0] - r) < 1e-6 and abs(st[-1] - r) < 1e-6
@@ -68,12 +78,13 @@ def test_random_mixed(orc, method, W, ng, seed):
     _check(c, 3, seed, orc, method)
 
 
+@pytest.mark.parametrize("method", ["fused", "fused_tables"])
 @pytest.mark.parametrize("k,m,cq", [(2, 4, 0), (3, 5, 1), (4, 6, 2), (5, 8, 3), (6, 9, 4),
                                     (5, 10, 5), (3, 11, 6), (5, 12, 5), (1, 12, 11), (16, 12, 0)])
-def test_fused_tile_shapes(orc, k, m, cq):
+def test_fused_tile_shapes(orc, method, k, m, cq):
     rng = np.random.default_rng(100 + m)
     c = I.random_mixed(13, 160, rng, n_inputs=4, p_input=0.2)
-    _check(c, 2, 100 + m, orc, "fused", fuse_width=k, tile_qubits=m, low_qubits=cq)
+    _check(c, 2, 100 + m, orc, method, fuse_width=k, tile_qubits=m, low_qubits=cq)
 
 
 @pytest.mark.parametrize("method", METHODS)
@@ -100,7 +111,7 @@ def test_product_state_closed_form_w20(method):
     c = I.rx_ry_rz_cz_ladder(W, 1)
     c.gates = [g for g in c.gates if g[0] != "CZ"]
     w, x = I.draw_angles(c, 4, 77)
-    got = gpu_run(c, w, x, 4, np.ones((4, W)), method=method)
+    got = gpu_run(c, w, x, 4, np.ones((4, W)), **_opts(method))
     w64, x64 = w.astype(np.float64), x.astype(np.float64)
     a = w64.reshape(W, 3)[:, 0][None, :]
     th = w64.reshape(W, 3)[:, 1][None, :]
@@ -124,7 +135,7 @@ def _sampled_full_size(orc, name, method, samples):
     g = np.zeros((batch, c.n_qubits))
     g[samples] = I.draw_grad_out(c, batch, seed)[samples]
     print(f"[parity] {name} sampled {samples} method={method}", flush=True)
-    got = gpu_run(c, w, x, batch, g, method=method)
+    got = gpu_run(c, w, x, batch, g, **_opts(method))
     ref = oracle_run(orc, c, w, x[samples], len(samples), g[samples])
     st = got["state"].cpu().numpy()[samples]
     assert np.abs(st - ref["state"]).max() <= AMP_TOL
@@ -148,13 +159,24 @@ def test_full_size_w16_b256_sampled(orc, method):
     _sampled_full_size(orc, "w16_b256_ring", method, [0, 101, 255])
 
 
-def test_fused_equals_per_gate_bitwise_deterministic(orc):
+@pytest.mark.parametrize("method", METHODS)
+def test_bitwise_deterministic(orc, method):
     # Two runs of the same plan give identical bits (no atomics on result paths).
     c = I.rx_ry_rz_cz_ladder(16, 3)
     w, x = I.draw_angles(c, 4, 5)
     g = I.draw_grad_out(c, 4, 5)
-    a = gpu_run(c, w, x, 4, g)
-    b = gpu_run(c, w, x, 4, g)
+    a = gpu_run(c, w, x, 4, g, **_opts(method))
+    b = gpu_run(c, w, x, 4, g, **_opts(method))
     assert np.array_equal(a["state"].cpu().numpy(), b["state"].cpu().numpy())
     assert np.array_equal(a["gw"].cpu().numpy(), b["gw"].cpu().numpy())
     assert np.array_equal(a["gx"].cpu().numpy(), b["gx"].cpu().numpy())
+
+
+def test_generated_equals_table_driven_state():
+    # Both fused kernel families apply the same ops in the same order per
+    # amplitude (they differ only in float32 contraction order).
+    c = I.ry_rz_cnot_ring(14, 3)
+    w, x = I.draw_angles(c, 3, 9)
+    a = gpu_run(c, w, x, 3, **_opts("fused"))
+    b = gpu_run(c, w, x, 3, **_opts("fused_tables"))
+    assert np.abs(a["state"].cpu().numpy() - b["state"].cpu().numpy()).max() < 2e-6
