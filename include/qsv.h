@@ -96,9 +96,12 @@ typedef struct {
 typedef struct {
     int32_t method;      /* QSV_METHOD_FUSED or QSV_METHOD_PER_GATE */
     int32_t fuse_width;  /* k: max qubits of a splitter block (section "Circuit
-                            Splitting" suggests 3..6); 1..16 */
+                            Splitting" suggests 3..6); 1..16. A gate with more
+                            qubits than k forms a block by itself, so k = 1
+                            packs gate by gate (1-qubit chains, single
+                            2-qubit gates), which gives the fewest passes */
     int32_t tile_qubits; /* m: qubits of one tile of amplitudes held by a
-                            workgroup, 4..12; clamped to W */
+                            workgroup, 4..14 (4..12 when codegen = 0); clamped to W */
     int32_t low_qubits;  /* c: number of lowest-stride qubits every tile keeps
                             (contiguous runs of 2^c amplitudes); 0..m-1 */
     int32_t max_pass_grads; /* cap on parametric gates per backward pass, 1..256 */
@@ -123,7 +126,7 @@ typedef struct {
 
 typedef struct qsv_plan_s qsv_plan_t;
 
-/* Fill *opts with the defaults (fused, k = 5, m = 12, c = 5, 256, codegen 1). */
+/* Fill *opts with the defaults (fused, k = 1, m = 12, c = 5, 256, codegen 1). */
 void qsv_default_opts(qsv_opts* opts);
 
 /*

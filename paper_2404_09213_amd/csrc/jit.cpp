@@ -111,6 +111,19 @@ __device__ __forceinline__ double qsv_wave_sum(double v) {
     const int lo = __builtin_amdgcn_readlane((int)x, 63), hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+// float32 sum over the 16 lanes of a DPP row (pairs, quads, half rows, rows);
+// every lane of the row ends with the row's total.
+template <int CTRL>
+__device__ __forceinline__ float qsv_dppf(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float qsv_row_sum(float v) {
+    v += qsv_dppf<0xB1>(v);
+    v += qsv_dppf<0x4E>(v);
+    v += qsv_dppf<0x141>(v);
+    v += qsv_dppf<0x140>(v);
+    return v;
+}
 __device__ __forceinline__ unsigned qsv_sgn(int f, int k) { return ((unsigned)(f >> k) & 1u) << 31; }
 __device__ __forceinline__ f2 qsv_flip(f2 a, unsigned s) {
     return make_float2(__uint_as_float(__float_as_uint(a.x) ^ s), __uint_as_float(__float_as_uint(a.y) ^ s));
@@ -368,7 +381,8 @@ private:
         o_ << "  __shared__ f2 lds[" << (1 << m_) << "];\n";
         int ng = bwd_ ? ps_->n_gslots : 0;
         const int nw = threads_ / 64;
-        if (bwd_ && ng) o_ << "  __shared__ double red[" << nw * ng << "];\n";
+        // per-row float32 partials of every gradient slot: [wave * 4 + row][slot]
+        if (bwd_ && ng) o_ << "  __shared__ float red[" << nw * 4 * ng << "];\n";
         o_ << "  const int t = threadIdx.x;\n";
         if (guard_) o_ << "  const bool act = t < " << T_ << ";\n";
         o_ << "  const unsigned tile = blockIdx.x;\n"
@@ -444,10 +458,11 @@ private:
                     emit_apply(op);
                 }
             }
-            // wavefront reductions of this stage's gradient partials (float64)
+            // row reductions of this stage's gradient partials (float32 within a
+            // 16-lane row); rows are combined in float64 at the end of the pass
             for (int j : stage_slots)
-                o_ << "  { const double r_ = qsv_wave_sum((double)g" << j << "); if (lane == 0) red[wave * " << ng
-                   << " + " << j << "] = r_; }\n";
+                o_ << "  { const float r_ = qsv_row_sum(g" << j << "); if ((lane & 15) == 0) red[(wave * 4 + (lane >> 4)) * "
+                   << ng << " + " << j << "] = r_; }\n";
         }
         const bool write_back = !bwd_ || !(flags & PF_LAST_BWD);
         if (write_back) {
@@ -463,7 +478,7 @@ private:
             o_ << "  {\n    const int* ord_ = " << name << "_ord;\n";
             o_ << "    for (int j = t; j < " << ng << "; j += " << threads_ << ") {\n"
                << "      double s = 0.0;\n";
-            for (int w = 0; w < nw; ++w) o_ << "      s += red[" << w * ng << " + j];\n";
+            for (int r = 0; r < nw * 4; ++r) o_ << "      s += (double)red[" << r * ng << " + j];\n";
             o_ << "      part[((size_t)ord_[j] * B + b) * " << (1u << tb) << "u + tis] = s;\n    }\n  }\n";
         }
         o_ << "}\n\n";

@@ -14,7 +14,8 @@ namespace qsv {
 
 constexpr int kRegBits = 4;            // amplitudes per thread in a tile = 2^kRegBits
 constexpr int kRegs = 1 << kRegBits;
-constexpr int kMaxTileQubits = 12;
+constexpr int kMaxTileQubits = 14;        // generated kernels
+constexpr int kMaxTileQubitsTables = 12;  // table-driven kernels (256 threads)
 constexpr int kMaxQ = 32;
 
 // ---- device-visible tables (plain old data, copied verbatim to the GPU) ----

@@ -563,10 +563,11 @@ int build_plan(qsv_plan_t* p) {
     // fused schedule
     const int m = std::min(o.tile_qubits, W);
     const int c = std::min(o.low_qubits, m - 1);
-    // LDS budget for per-wave gradient partials: (threads / 64) x grads x 8 bytes
+    // LDS budget for gradient partials per slot: float32 per 16-lane row
+    // (generated kernels) or float64 per wave (table-driven) = threads / 4 bytes
     const int threads = std::max(64, 1 << (m - kRegBits));
     const int exch = (1 << m) * 8;
-    int max_grads = std::min(o.max_pass_grads, (160 * 1024 - exch) / ((threads / 64) * 8));
+    int max_grads = std::min(o.max_pass_grads, (160 * 1024 - exch) / (threads / 4));
     max_grads = std::max(max_grads, 1);
     {
         std::vector<uint32_t> dense;

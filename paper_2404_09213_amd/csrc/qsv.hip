@@ -1158,7 +1158,7 @@ void qsv_default_opts(qsv_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
     o->method = QSV_METHOD_FUSED;
-    o->fuse_width = 5;
+    o->fuse_width = 1;
     o->tile_qubits = 12;
     o->low_qubits = 5;
     o->max_pass_grads = 256;
@@ -1177,11 +1177,12 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     qsv_default_opts(&o);
     if (opts) o = *opts;
     if (o.method != QSV_METHOD_FUSED && o.method != QSV_METHOD_PER_GATE) { set_error("bad method"); return QSV_ERR_ARG; }
+    if (o.codegen != 0 && o.codegen != 1) { set_error("codegen must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.fuse_width < 1 || o.fuse_width > 16) { set_error("fuse_width must be in 1..16"); return QSV_ERR_ARG; }
-    if (o.tile_qubits < kRegBits || o.tile_qubits > kMaxTileQubits) { set_error("tile_qubits must be in 4..12"); return QSV_ERR_ARG; }
+    if (o.tile_qubits < kRegBits || o.tile_qubits > kMaxTileQubits) { set_error("tile_qubits must be in 4..14"); return QSV_ERR_ARG; }
+    if (o.codegen == 0 && o.tile_qubits > kMaxTileQubitsTables) { set_error("table-driven kernels (codegen 0) need tile_qubits <= 12"); return QSV_ERR_ARG; }
     if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
-    if (o.codegen != 0 && o.codegen != 1) { set_error("codegen must be 0 or 1"); return QSV_ERR_ARG; }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];

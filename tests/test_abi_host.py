@@ -66,7 +66,7 @@ def test_plan_rejects(lib, W, gate, code):
 
 def test_plan_rejects_bad_options(lib):
     for field, val in [("fuse_width", 0), ("fuse_width", 17), ("tile_qubits", 3),
-                       ("tile_qubits", 13), ("low_qubits", 12), ("method", 2), ("codegen", 2),
+                       ("tile_qubits", 15), ("low_qubits", 12), ("method", 2), ("codegen", 2),
                        ("max_pass_grads", 0)]:
         o = B.qsv_default_opts()
         setattr(o, field, val)

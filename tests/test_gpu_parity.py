@@ -87,6 +87,15 @@ def test_fused_tile_shapes(orc, method, k, m, cq):
     _check(c, 2, 100 + m, orc, method, fuse_width=k, tile_qubits=m, low_qubits=cq)
 
 
+@pytest.mark.parametrize("k,m,cq", [(1, 13, 5), (1, 14, 6), (2, 13, 4), (5, 14, 3)])
+def test_generated_large_tiles(orc, k, m, cq):
+    # 512- and 1024-thread tiles (generated kernels only)
+    rng = np.random.default_rng(200 + m)
+    c = I.random_mixed(16, 140, rng, n_inputs=3, p_input=0.2)
+    _check(c, 2, 200 + m, orc, "fused", fuse_width=k, tile_qubits=m, low_qubits=cq)
+    _check(I.rx_ry_rz_cz_ladder(16, 3), 2, 7, orc, "fused", fuse_width=k, tile_qubits=m, low_qubits=cq)
+
+
 @pytest.mark.parametrize("method", METHODS)
 def test_ladder_and_ring_small(orc, method):
     _check(I.rx_ry_rz_cz_ladder(14, 4), 3, 1003, orc, method)
