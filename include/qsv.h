@@ -122,7 +122,16 @@ typedef struct {
     int32_t n_bwd_stages;
     int32_t n_param_gates;    /* gates with src != NONE */
     int32_t n_recipes;        /* cached gate-matrix products evaluated per call */
+    int32_t n_circuits;       /* 1, or the number of circuits of a multi-circuit plan */
 } qsv_plan_info;
+
+/* One circuit of a multi-circuit plan. */
+typedef struct {
+    int32_t n_qubits;         /* 4..QSV_MAX_QUBITS */
+    int32_t n_gates;
+    const qsv_gate* gates;    /* host memory, read during qsv_plan_multi only */
+    int32_t n_weights, n_inputs;
+} qsv_circuit;
 
 typedef struct qsv_plan_s qsv_plan_t;
 
@@ -142,6 +151,31 @@ void qsv_default_opts(qsv_opts* opts);
  */
 int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n_weights,
              int32_t n_inputs, const qsv_opts* opts, qsv_plan_t** out);
+
+/*
+ * Plan for many circuits of different sizes and depths simulated together
+ * (the uneven batch). Every circuit is split and scheduled as by qsv_plan
+ * (fused method, table-driven kernels, tile_qubits <= 12). qsv_forward and
+ * qsv_backward then run pass r of EVERY circuit in one launch ("round r"),
+ * one workgroup per (circuit, tile); a circuit's next pass is in the next
+ * round, so the number of launches per direction is the largest pass count of
+ * any circuit, not the number of circuits. No workgroup waits on another.
+ * Layouts with the plan (c = circuit, prefix sums over earlier circuits):
+ *   weights:      concatenation of every circuit's weights;
+ *   inputs:       batch x (sum of n_inputs), circuit c's columns after c-1's;
+ *   state:        batch x (sum of 2^n_qubits) complex64, circuit c's
+ *                 amplitudes at qsv_plan_circuit_offsets(...amp);
+ *   expectations, grad_out: batch x (sum of n_qubits), float64;
+ *   gradients:    weights and inputs laid out as above.
+ * Each circuit's results equal those of a single plan of that circuit.
+ */
+int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* opts,
+                   qsv_plan_t** out);
+
+/* Offsets of circuit `circuit` in the layouts above (single plans: all 0).
+ * Any output pointer may be NULL. */
+int qsv_plan_circuit_offsets(const qsv_plan_t* plan, int32_t circuit, int64_t* amp_offset,
+                             int32_t* qubit_offset, int32_t* weight_offset, int32_t* input_offset);
 
 /* Release a plan and its device tables. NULL is ignored. */
 void qsv_plan_destroy(qsv_plan_t* plan);

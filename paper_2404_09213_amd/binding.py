@@ -51,7 +51,13 @@ class qsv_plan_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "n_qubits", "n_gates", "n_weights", "n_inputs", "method", "fuse_width", "tile_qubits",
         "low_qubits", "n_prefix_gates", "n_blocks", "n_fwd_passes", "n_bwd_passes",
-        "n_fwd_stages", "n_bwd_stages", "n_param_gates", "n_recipes")]
+        "n_fwd_stages", "n_bwd_stages", "n_param_gates", "n_recipes", "n_circuits")]
+
+
+class qsv_circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("gates", ctypes.POINTER(qsv_gate)), ("n_weights", ctypes.c_int32),
+                ("n_inputs", ctypes.c_int32)]
 
 
 class qsv_kernel_stat(ctypes.Structure):
@@ -60,7 +66,8 @@ class qsv_kernel_stat(ctypes.Structure):
                 ("flops", ctypes.c_double)]
 
 
-EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_destroy", "qsv_workspace_size",
+EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets",
+           "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
            "qsv_plan_codegen_check", "qsv_profile_enable",
@@ -82,6 +89,12 @@ def lib():
         L.qsv_plan.argtypes = [i32, ctypes.POINTER(qsv_gate), i32, i32, i32,
                                ctypes.POINTER(qsv_opts), ctypes.POINTER(vp)]
         L.qsv_plan.restype = ctypes.c_int
+        L.qsv_plan_multi.argtypes = [ctypes.POINTER(qsv_circuit), i32, ctypes.POINTER(qsv_opts),
+                                     ctypes.POINTER(vp)]
+        L.qsv_plan_multi.restype = ctypes.c_int
+        L.qsv_plan_circuit_offsets.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                               ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.qsv_plan_circuit_offsets.restype = ctypes.c_int
         L.qsv_plan_destroy.argtypes = [vp]
         L.qsv_plan_destroy.restype = None
         L.qsv_workspace_size.argtypes = [vp, i64, i32]
@@ -140,6 +153,35 @@ def qsv_plan(n_qubits, gates, n_weights, n_inputs, opts=None):
     _check(lib().qsv_plan(int(n_qubits), arr, n, int(n_weights), int(n_inputs),
                           ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
     return h
+
+
+def _gate_array(gates):
+    n = len(gates)
+    arr = (qsv_gate * max(n, 1))()
+    for i, (k, q0, q1, s, idx) in enumerate(gates):
+        arr[i] = qsv_gate(KIND[k] if isinstance(k, str) else int(k), int(q0), int(q1),
+                          SRC[s] if isinstance(s, str) else int(s), int(idx))
+    return arr
+
+
+def qsv_plan_multi(circuits, opts=None):
+    """circuits: sequence of (n_qubits, gates, n_weights, n_inputs)."""
+    keep = [_gate_array(g) for (_, g, _, _) in circuits]
+    arr = (qsv_circuit * len(circuits))()
+    for i, (n, g, nw, ni) in enumerate(circuits):
+        arr[i] = qsv_circuit(int(n), len(g), ctypes.cast(keep[i], ctypes.POINTER(qsv_gate)),
+                             int(nw), int(ni))
+    h = ctypes.c_void_p()
+    _check(lib().qsv_plan_multi(arr, len(circuits), ctypes.byref(opts) if opts is not None else None,
+                                ctypes.byref(h)))
+    return h
+
+
+def qsv_plan_circuit_offsets(h, circuit):
+    a, q, w, x = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().qsv_plan_circuit_offsets(h, int(circuit), ctypes.byref(a), ctypes.byref(q),
+                                          ctypes.byref(w), ctypes.byref(x)))
+    return {"amp": a.value, "qubit": q.value, "weight": w.value, "input": x.value}
 
 
 def qsv_plan_destroy(h):
@@ -246,6 +288,8 @@ class Plan:
         self.n_inputs = int(n_inputs)
         self.opts = make_opts(**opts)
         self.handle = qsv_plan(n_qubits, gates, n_weights, n_inputs, self.opts)
+        self.state_len = 1 << self.n_qubits   # amplitudes per sample
+        self.n_out = self.n_qubits            # expectation columns per sample
         self._ws = {}
 
     def __del__(self):
@@ -293,7 +337,7 @@ class Plan:
         import torch
         dev = weights.device if weights is not None and weights.numel() else inputs.device
         if state is None:
-            state = torch.empty((batch, 1 << self.n_qubits), dtype=torch.complex64, device=dev)
+            state = torch.empty((batch, self.state_len), dtype=torch.complex64, device=dev)
         ws = self.workspace(batch, OP_FORWARD, dev)
         qsv_forward(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
                     self._ptr(state), self._ptr(ws), ws.numel(), self._stream(dev))
@@ -303,7 +347,7 @@ class Plan:
         import torch
         batch = state.shape[0]
         if out is None:
-            out = torch.empty((batch, self.n_qubits), dtype=torch.float64, device=state.device)
+            out = torch.empty((batch, self.n_out), dtype=torch.float64, device=state.device)
         ws = self.workspace(batch, OP_EXPVAL, state.device)
         qsv_expval(self.handle, self._ptr(state), batch, self._ptr(out), self._ptr(ws), ws.numel(),
                    self._stream(state.device))
@@ -331,3 +375,26 @@ def _f32(t):
     import torch
     assert t.dtype == torch.float32 and t.is_contiguous(), "angles must be contiguous float32"
     return t
+
+
+class MultiPlan(Plan):
+    """Many circuits simulated together (one launch per round of passes).
+
+    circuits: sequence of inputs.Circuit (or objects with n_qubits, gates,
+    n_weights, n_inputs). Layouts are documented with qsv_plan_multi.
+    """
+
+    def __init__(self, circuits, **opts):
+        self.opts = make_opts(**opts)
+        spec = [(c.n_qubits, c.gates, c.n_weights, c.n_inputs) for c in circuits]
+        self.handle = qsv_plan_multi(spec, self.opts)
+        self.n_circuits = len(spec)
+        self.n_gates = sum(len(c[1]) for c in spec)
+        self.n_weights = sum(c[2] for c in spec)
+        self.n_inputs = sum(c[3] for c in spec)
+        self.n_qubits = sum(c[0] for c in spec)
+        self.offsets = [qsv_plan_circuit_offsets(self.handle, i) for i in range(len(spec))]
+        self.sizes = [c[0] for c in spec]
+        self.state_len = self.offsets[-1]["amp"] + (1 << spec[-1][0])
+        self.n_out = self.n_qubits
+        self._ws = {}

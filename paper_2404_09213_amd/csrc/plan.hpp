@@ -104,6 +104,24 @@ struct PGate {
     int32_t sh2;        // CZ second shift
 };
 
+// One circuit of a multi-circuit plan.
+struct DCirc {
+    int32_t W, m;           // qubits, tile qubits
+    int32_t n_fwd, n_bwd;   // passes
+    int32_t fwd0, bwd0;     // first pass in the concatenated pass arrays
+    int32_t e0;             // first expectation column (sum of earlier circuits' qubits)
+    int32_t pm0;            // first prefix-matrix entry
+    int64_t amp0;           // amplitude offset within a sample row
+    int32_t ic0;            // first readout / init chunk (chunks of 2^min(W,12) amplitudes)
+    int32_t nchunk;         // chunks per sample
+};
+
+// A work item of a multi-circuit launch: one tile of one pass of one circuit.
+struct DItem {
+    int32_t c, pass, tile;  // circuit, pass index within the circuit, tile within the pass
+    int32_t pad[3];
+};
+
 // ---- host plan ----
 
 struct Block {
@@ -124,6 +142,18 @@ struct DeviceTables {
     int32_t* gslot_map = nullptr;
     int32_t* prefix_mat = nullptr;
     int32_t* grad_csr = nullptr;   // weights then inputs: offsets, then slot lists
+    int64_t* pu = nullptr;         // per parametric ordinal: partial offset in units of B
+    int32_t* nchv = nullptr;       // per parametric ordinal: partial chunks per sample
+    DCirc* circ = nullptr;         // multi-circuit plans
+    // multi-circuit work lists per batch size, grouped in rounds (item offsets)
+    struct Queue {
+        int64_t B;
+        DItem* fwd; int n_fwd;
+        DItem* bwd; int n_bwd;
+        void* mem;
+        std::vector<int> fwd_rounds, bwd_rounds;
+    };
+    std::vector<Queue> queues;
     // generated pass kernels (hipModule_t / hipFunction_t, kept opaque here)
     std::vector<void*> modules;
     std::vector<void*> fwd_fn, bwd_fn;
@@ -177,13 +207,35 @@ struct qsv_plan_s {
     // profiling state (opaque; owned by the HIP side)
     mutable void* prof = nullptr;
 
+    // gradient partial layout (all methods): ordinal o, sample b, chunk k at
+    // part[B * pu[o] + b * nchv[o] + k]
+    std::vector<int64_t> pu;
+    std::vector<int32_t> nchv;
+    int64_t pu_total = 0;
+
+    // multi-circuit plans: circuits simulated together by persistent launches
+    bool multi = false;
+    std::vector<qsv::DCirc> circ;
+    int Wtot = 0;          // expectation columns (sum of qubits)
+    int64_t row = 0;       // amplitudes per sample row (sum of 2^W)
+    int64_t nchunk_tot = 0;
+    int n_fwd_tot = 0, n_bwd_tot = 0;  // passes over all circuits
+    std::vector<int32_t> circ_w0, circ_x0;  // first weight / input column of each circuit
+
     // lazily created device copies, per device ordinal
     mutable std::mutex dev_mu;
     mutable std::map<int, qsv::DeviceTables> dev;
 };
 
 namespace qsv {
+// chunks per sample of the plain method's gradient partials
+inline int64_t pg_chunks(int W) {
+    const int64_t q = int64_t(1) << (W - 2 > 0 ? W - 2 : 0);
+    return q / 1024 > 1 ? q / 1024 : 1;
+}
 constexpr uint32_t kPlanMagic = 0x51535650u;  // "QSVP"
-int build_plan(qsv_plan_t* p);                  // planner.cpp
+int build_plan(qsv_plan_t* p);  // planner.cpp
+struct CircuitIn { int W; const qsv_gate* gates; int n_gates, n_weights, n_inputs; };
+int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs);  // planner.cpp
 void set_error(const std::string& msg);       // api
 }  // namespace qsv

@@ -453,6 +453,13 @@ double pg_flops(const PGate& g, bool backward) {
     return f;
 }
 
+void set_partial_layout(qsv_plan_t* p, int64_t nch) {
+    p->pu.resize(p->n_param);
+    p->nchv.assign(p->n_param, (int32_t)nch);
+    for (int o = 0; o < p->n_param; ++o) p->pu[o] = (int64_t)o * nch;
+    p->pu_total = (int64_t)p->n_param * nch;
+}
+
 int pg_class(const qsv_plan_t* p, int g) {
     const int k = p->gates[g].kind;
     if (k == QSV_CZ) return OP_SIGN;
@@ -557,6 +564,7 @@ int build_plan(qsv_plan_t* p) {
         }
         for (auto& x : p->pg_fwd) p->pg_fwd_flops.push_back(pg_flops(x, false));
         for (auto& x : p->pg_bwd) p->pg_bwd_flops.push_back(pg_flops(x, true));
+        set_partial_layout(p, pg_chunks(W));
         return QSV_OK;
     }
 
@@ -596,6 +604,155 @@ int build_plan(qsv_plan_t* p) {
         p->n_bwd_stages += ps.n_stages;
         p->bwd_pass_flops.push_back(pass_flops(p, ps, true));
     }
+    set_partial_layout(p, int64_t(1) << (W - m));
+    return QSV_OK;
+}
+
+// Many circuits in one plan: each circuit is planned on its own (fused,
+// table-driven kernels), then the tables are concatenated with every index
+// shifted to the combined numbering. Weights and input columns of circuit c
+// follow those of circuits 0..c-1; a sample row of the state holds every
+// circuit's 2^W amplitudes back to back, and a row of expectations every
+// circuit's qubits.
+int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs) {
+    p->multi = true;
+    int w0 = 0, x0 = 0, e0 = 0, ord0 = 0, chunk0 = 0;
+    int64_t amp0 = 0;
+    std::vector<int> wl_off, xl_off;
+    std::vector<std::vector<int>> wl, xl;
+    for (size_t c = 0; c < cs.size(); ++c) {
+        const CircuitIn& ci = cs[c];
+        qsv_plan_t sub;
+        sub.magic = kPlanMagic;
+        sub.W = ci.W;
+        sub.n_gates = ci.n_gates;
+        sub.n_weights = ci.n_weights;
+        sub.n_inputs = ci.n_inputs;
+        sub.opts = p->opts;
+        sub.opts.method = QSV_METHOD_FUSED;
+        sub.opts.codegen = 0;
+        sub.opts.tile_qubits = std::min(sub.opts.tile_qubits, (int32_t)kMaxTileQubitsTables);
+        sub.gates.assign(ci.gates, ci.gates + ci.n_gates);
+        int rc = build_plan(&sub);
+        if (rc != QSV_OK) return rc;
+        DCirc d;
+        std::memset(&d, 0, sizeof d);
+        d.W = ci.W;
+        d.m = std::min((int)sub.opts.tile_qubits, ci.W);
+        d.n_fwd = (int32_t)sub.fwd_pass.size();
+        d.n_bwd = (int32_t)sub.bwd_pass.size();
+        d.fwd0 = (int32_t)p->fwd_pass.size();
+        d.bwd0 = (int32_t)p->bwd_pass.size();
+        d.e0 = e0;
+        d.pm0 = (int32_t)p->prefix_mat.size();
+        d.amp0 = amp0;
+        d.ic0 = chunk0;
+        d.nchunk = 1 << (ci.W - std::min(ci.W, 12));
+        const int g0 = (int)p->dgates.size(), rg0 = (int)p->recipe_gates.size();
+        const int st0 = (int)p->stages.size(), op0 = (int)p->ops.size(), t0 = (int)p->terms.size();
+        const int gs0 = (int)p->gslot_map.size();
+        const int sh0 = p->n_shared_mats, ps0 = p->n_ps_mats;
+        auto fix_mat = [&](int32_t mat) { return mat >= 0 ? mat + sh0 : -((-mat - 1) + ps0) - 1; };
+        for (DGate g : sub.dgates) {
+            if (g.src == QSV_SRC_WEIGHT) g.idx += w0;
+            if (g.src == QSV_SRC_INPUT) g.idx += x0;
+            p->dgates.push_back(g);
+        }
+        for (int32_t g : sub.recipe_gates) p->recipe_gates.push_back(g + g0);
+        for (DRecipe r : sub.recipes) {
+            r.first += rg0;
+            r.out = fix_mat(r.out);
+            p->recipes.push_back(r);
+        }
+        p->n_shared_mats += sub.n_shared_mats;
+        p->n_ps_mats += sub.n_ps_mats;
+        for (int32_t m : sub.prefix_mat) p->prefix_mat.push_back(fix_mat(m));
+        for (DStage st : sub.stages) {
+            st.op0 += op0;
+            st.op1 += op0;
+            p->stages.push_back(st);
+        }
+        for (DOp o : sub.ops) {
+            if (o.kind != OP_SIGN && o.kind != OP_SWAP && o.kind < OP_GX) o.mat = fix_mat(o.mat);
+            if (o.kind == OP_SIGN) o.term0 += t0;
+            p->ops.push_back(o);
+        }
+        p->terms.insert(p->terms.end(), sub.terms.begin(), sub.terms.end());
+        for (int32_t o : sub.gslot_map) p->gslot_map.push_back(o + ord0);
+        for (DPass ps : sub.fwd_pass) {
+            ps.stage0 += st0;
+            ps.gslot0 += gs0;
+            p->fwd_pass.push_back(ps);
+        }
+        for (DPass ps : sub.bwd_pass) {
+            ps.stage0 += st0;
+            ps.gslot0 += gs0;
+            p->bwd_pass.push_back(ps);
+        }
+        p->fwd_pass_flops.insert(p->fwd_pass_flops.end(), sub.fwd_pass_flops.begin(), sub.fwd_pass_flops.end());
+        p->bwd_pass_flops.insert(p->bwd_pass_flops.end(), sub.bwd_pass_flops.begin(), sub.bwd_pass_flops.end());
+        // parametric ordinals, gradient lists and partial layout
+        const int64_t nch = int64_t(1) << (ci.W - d.m);
+        for (int o = 0; o < sub.n_param; ++o) {
+            p->pu.push_back(p->pu_total);
+            p->nchv.push_back((int32_t)nch);
+            p->pu_total += nch;
+            const int g = sub.param_gate[o];
+            const qsv_gate& G = sub.gates[g];
+            p->param_gate.push_back(g0 + g);
+            if (G.src == QSV_SRC_WEIGHT) {
+                if ((int)wl.size() < w0 + G.idx + 1) wl.resize(w0 + G.idx + 1);
+                wl[w0 + G.idx].push_back(ord0 + o);
+            } else {
+                if ((int)xl.size() < x0 + G.idx + 1) xl.resize(x0 + G.idx + 1);
+                xl[x0 + G.idx].push_back(ord0 + o);
+            }
+        }
+        for (int g = 0; g < ci.n_gates; ++g) {
+            p->gates.push_back(ci.gates[g]);
+            p->param_ordinal.push_back(sub.param_ordinal[g] >= 0 ? sub.param_ordinal[g] + ord0 : -1);
+            p->block_of_gate.push_back(sub.block_of_gate[g] + (int32_t)p->blocks.size());
+        }
+        for (const Block& b : sub.blocks) {
+            Block nb = b;
+            for (int& g : nb.gates) g += g0;
+            p->blocks.push_back(nb);
+        }
+        for (int32_t g : sub.fwd_order) p->fwd_order.push_back(g + g0);
+        for (int32_t g : sub.bwd_order) p->bwd_order.push_back(g + g0);
+        for (int g : sub.prefix_gates) p->prefix_gates.push_back(g + g0);
+        p->n_fwd_stages += sub.n_fwd_stages;
+        p->n_bwd_stages += sub.n_bwd_stages;
+        p->circ.push_back(d);
+        p->circ_w0.push_back(w0);
+        p->circ_x0.push_back(x0);
+        w0 += ci.n_weights;
+        x0 += ci.n_inputs;
+        e0 += ci.W;
+        ord0 += sub.n_param;
+        chunk0 += d.nchunk;
+        amp0 += int64_t(1) << ci.W;
+    }
+    p->n_param = ord0;
+    p->n_gates = (int)p->gates.size();
+    p->n_weights = w0;
+    p->n_inputs = x0;
+    p->Wtot = e0;
+    p->row = amp0;
+    p->nchunk_tot = chunk0;
+    p->n_fwd_tot = (int)p->fwd_pass.size();
+    p->n_bwd_tot = (int)p->bwd_pass.size();
+    wl.resize(w0);
+    xl.resize(x0);
+    const int head = w0 + 1 + x0 + 1;
+    p->grad_csr.assign(head, 0);
+    int at = head;
+    for (int j = 0; j < w0; ++j) { p->grad_csr[j] = at; at += (int)wl[j].size(); }
+    p->grad_csr[w0] = at;
+    for (int j = 0; j < x0; ++j) { p->grad_csr[w0 + 1 + j] = at; at += (int)xl[j].size(); }
+    p->grad_csr[w0 + 1 + x0] = at;
+    for (auto& l : wl) p->grad_csr.insert(p->grad_csr.end(), l.begin(), l.end());
+    for (auto& l : xl) p->grad_csr.insert(p->grad_csr.end(), l.begin(), l.end());
     return QSV_OK;
 }
 

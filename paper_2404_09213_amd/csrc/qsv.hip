@@ -231,9 +231,12 @@ __global__ __launch_bounds__(256) void k_expval_final(const double* __restrict__
 // ----------------------------------------------------------------------------
 // gradient reduction: partials[(ordinal * B + b) * nch + chunk]
 // ----------------------------------------------------------------------------
+// Partial of ordinal o, sample b, chunk k at part[B * pu[o] + b * nch[o] + k].
 __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ part,
                                                      const int32_t* __restrict__ csr, int n_weights,
-                                                     int n_inputs, int B, int64_t nch,
+                                                     int n_inputs, int B,
+                                                     const int64_t* __restrict__ pu,
+                                                     const int32_t* __restrict__ nchv,
                                                      double* __restrict__ gw,
                                                      double* __restrict__ gx) {
     __shared__ double red[256];
@@ -259,9 +262,11 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
         b0 = b;
         b1 = b + 1;
     }
-    const int64_t per = (int64_t)(b1 - b0) * nch;
     for (int l = 0; l < nl; ++l) {
-        const double* base = part + ((size_t)list[l] * B + b0) * nch;
+        const int o = list[l];
+        const int64_t nch = nchv[o];
+        const int64_t per = (int64_t)(b1 - b0) * nch;
+        const double* base = part + (int64_t)B * pu[o] + (int64_t)b0 * nch;
         for (int64_t e = t; e < per; e += 256) s += base[e];
     }
     red[t] = s;
@@ -747,22 +752,19 @@ __device__ __forceinline__ int tile_base_of(const DPass* __restrict__ P, int tbi
     return base;
 }
 
-__global__ __launch_bounds__(1024) void k_pass_fwd(const DPass* __restrict__ P,
-                                                   const DStage* __restrict__ S,
-                                                   const DOp* __restrict__ O,
-                                                   const DTerm* __restrict__ Tm,
-                                                   const float* __restrict__ mats, int n_shared,
-                                                   int n_ps, float2* __restrict__ state, int W) {
-    extern __shared__ float2 lds[];
+// One fused forward pass over one tile of one sample. st: the sample's 2^W
+// amplitudes; tis: tile index within the sample; lds: 2^m float2.
+__device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
+                                              const DStage* __restrict__ S,
+                                              const DOp* __restrict__ O,
+                                              const DTerm* __restrict__ Tm,
+                                              const float* __restrict__ mats, int n_shared,
+                                              int n_ps, float2* __restrict__ st, int W, int b,
+                                              int64_t tis, float2* lds) {
     const int m = P->m;
     const int t = threadIdx.x;
     const bool act = t < (1 << (m - kRegBits));
-    const int tbits = W - m;
-    const int64_t tile = blockIdx.x;
-    const int b = (int)(tile >> tbits);
-    const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
-    const int base = tile_base_of(P, tbits, tis);
-    float2* st = state + ((size_t)b << W);
+    const int base = tile_base_of(P, W - m, tis);
 
     int cur[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
     Lay L;
@@ -794,17 +796,23 @@ __global__ __launch_bounds__(1024) void k_pass_fwd(const DPass* __restrict__ P,
         __syncthreads();
         make_layout(P, m, nat, t, base, L);
         if (act) lds_load(lds, L, a);
+        __syncthreads();
     }
     if (act) g_store(st, L, a);
 }
 
-__global__ __launch_bounds__(256) void k_pass_bwd(
+// One fused backward pass over one tile of one sample. psiN_s / psi_s / lam_s:
+// the sample's vectors; g: the sample's W upstream gradients. The partial of
+// gradient slot j goes to part[B * pu[ord] + b * nch + tis] with ord its
+// parametric-gate ordinal. lds: 2^m float2 followed by (blockDim/64) x
+// n_gslots doubles.
+__device__ __forceinline__ void pass_bwd_tile(
     const DPass* __restrict__ P, const DStage* __restrict__ S, const DOp* __restrict__ O,
     const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
-    const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
-    float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int W,
-    int B, double* __restrict__ part) {
-    extern __shared__ float2 lds[];
+    const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN_s,
+    float2* __restrict__ psi_s, float2* __restrict__ lam_s, const double* __restrict__ g, int W,
+    int64_t B, int b, int64_t tis, double* __restrict__ part, const int64_t* __restrict__ pu,
+    float2* lds) {
     const int m = P->m;
     const int t = threadIdx.x;
     const int nthr = 1 << (m - kRegBits);
@@ -812,11 +820,7 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
     const int nwaves = (int)(blockDim.x >> 6);
     double* red = reinterpret_cast<double*>(lds + (1 << m));
     const int tbits = W - m;
-    const int64_t tile = blockIdx.x;
-    const int b = (int)(tile >> tbits);
-    const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
     const int base = tile_base_of(P, tbits, tis);
-    const size_t off = (size_t)b << W;
     const int flags = P->flags;
 
     int cur[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
@@ -826,9 +830,8 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
     for (int k = 0; k < kRegs; ++k) ps[k] = lm[k] = make_float2(0.f, 0.f);
     if (act) {
         if (flags & PF_FIRST_BWD) {
-            g_load(psiN + off, L, ps);
+            g_load(psiN_s, L, ps);
             // lambda = D psi, D(idx) = G0 - 2 sum_{i: bit_i = 1} g_i (additive over bits)
-            const double* g = gout + (size_t)b * W;
             double G0 = 0.0, DT = 0.0;
             for (int i = 0; i < W; ++i) {
                 G0 += g[i];
@@ -845,8 +848,8 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
                 lm[k] = make_float2(d * ps[k].x, d * ps[k].y);
             }
         } else {
-            g_load(psi + off, L, ps);
-            g_load(lam + off, L, lm);
+            g_load(psi_s, L, ps);
+            g_load(lam_s, L, lm);
         }
     }
     const int wave = t >> 6, lane = t & 63;
@@ -894,8 +897,8 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
             L = Ln;
         }
         if (act) {
-            g_store(psi + off, L, ps);
-            g_store(lam + off, L, lm);
+            g_store(psi_s, L, ps);
+            g_store(lam_s, L, lm);
         }
     }
     __syncthreads();
@@ -904,8 +907,190 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
     for (int j = t; j < ng; j += blockDim.x) {
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w) s += red[w * ng + j];
-        part[((size_t)gslot_map[P->gslot0 + j] * B + b) * nch + tis] = s;
+        part[B * pu[gslot_map[P->gslot0 + j]] + (int64_t)b * nch + tis] = s;
     }
+    __syncthreads();  // red and lds may be reused by the caller's next tile
+}
+
+__global__ __launch_bounds__(1024) void k_pass_fwd(const DPass* __restrict__ P,
+                                                   const DStage* __restrict__ S,
+                                                   const DOp* __restrict__ O,
+                                                   const DTerm* __restrict__ Tm,
+                                                   const float* __restrict__ mats, int n_shared,
+                                                   int n_ps, float2* __restrict__ state, int W) {
+    extern __shared__ float2 lds[];
+    const int tbits = W - P->m;
+    const int64_t tile = blockIdx.x;
+    const int b = (int)(tile >> tbits);
+    const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
+    pass_fwd_tile(P, S, O, Tm, mats, n_shared, n_ps, state + ((size_t)b << W), W, b, tis, lds);
+}
+
+__global__ __launch_bounds__(256) void k_pass_bwd(
+    const DPass* __restrict__ P, const DStage* __restrict__ S, const DOp* __restrict__ O,
+    const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
+    const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
+    float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int W,
+    int B, double* __restrict__ part, const int64_t* __restrict__ pu) {
+    extern __shared__ float2 lds[];
+    const int tbits = W - P->m;
+    const int64_t tile = blockIdx.x;
+    const int b = (int)(tile >> tbits);
+    const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
+    const size_t off = (size_t)b << W;
+    pass_bwd_tile(P, S, O, Tm, gslot_map, mats, n_shared, n_ps, psiN + off, psi + off, lam + off,
+                  gout + (size_t)b * W, W, B, b, tis, part, pu, lds);
+}
+
+// ----------------------------------------------------------------------------
+// many circuits, one launch per round
+// ----------------------------------------------------------------------------
+// Round r holds tile items of pass r of every circuit that has one; workgroup
+// i of the launch processes item i. Pass r + 1 of a circuit only starts in the
+// next launch, so kernel boundaries order the passes; no workgroup waits on
+// another.
+__global__ __launch_bounds__(256) void k_multi_fwd(
+    const DCirc* __restrict__ C, const DItem* __restrict__ Q,
+    const DPass* __restrict__ passes, const DStage* __restrict__ S, const DOp* __restrict__ O,
+    const DTerm* __restrict__ Tm, const float* __restrict__ mats, int n_shared, int n_ps,
+    float2* __restrict__ state, int64_t row) {
+    extern __shared__ float2 lds[];
+    const DItem I = Q[blockIdx.x];
+    const DCirc& c = C[I.c];
+    const int tbits = c.W - c.m;
+    const int b = I.tile >> tbits;
+    const int64_t tis = I.tile & ((1 << tbits) - 1);
+    pass_fwd_tile(passes + c.fwd0 + I.pass, S, O, Tm, mats, n_shared, n_ps,
+                  state + (size_t)b * row + c.amp0, c.W, b, tis, lds);
+}
+
+__global__ __launch_bounds__(256) void k_multi_bwd(
+    const DCirc* __restrict__ C, const DItem* __restrict__ Q,
+    const DPass* __restrict__ passes, const DStage* __restrict__ S, const DOp* __restrict__ O,
+    const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
+    const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
+    float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int Wtot,
+    int64_t row, int B, double* __restrict__ part, const int64_t* __restrict__ pu) {
+    extern __shared__ float2 lds[];
+    const DItem I = Q[blockIdx.x];
+    const DCirc& c = C[I.c];
+    const int tbits = c.W - c.m;
+    const int b = I.tile >> tbits;
+    const int64_t tis = I.tile & ((1 << tbits) - 1);
+    const size_t off = (size_t)b * row + c.amp0;
+    pass_bwd_tile(passes + c.bwd0 + I.pass, S, O, Tm, gslot_map, mats, n_shared, n_ps, psiN + off,
+                  psi + off, lam + off, gout + (size_t)b * Wtot + c.e0, c.W, B, b, tis, part, pu, lds);
+}
+
+// product-state init of every circuit: grid (sum of per-circuit chunks, B)
+__global__ __launch_bounds__(256) void k_init_multi(const DCirc* __restrict__ C, int n_circ,
+                                                    float2* __restrict__ state, int64_t row,
+                                                    const int32_t* __restrict__ pm,
+                                                    const float* __restrict__ mats, int n_shared,
+                                                    int n_ps) {
+    // find the circuit owning this chunk (chunk prefix in DCirc.ic0)
+    int lo = 0, hi = n_circ - 1;
+    const int x = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (C[mid].ic0 <= x) lo = mid; else hi = mid - 1;
+    }
+    const DCirc& c = C[lo];
+    const int W = c.W;
+    const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
+    const int t = threadIdx.x;
+    if (t >= (1 << tb)) return;
+    const int b = blockIdx.y;
+    const int64_t chunk = x - c.ic0;
+    const int32_t* pmc = pm + c.pm0;
+    float2 P = make_float2(1.f, 0.f);
+    for (int s = 0; s < tb; ++s) P = cmul(P, prefix_v(mats, pmc, W - 1 - s, (t >> s) & 1, b, n_shared, n_ps));
+    for (int s = cb; s < W; ++s)
+        P = cmul(P, prefix_v(mats, pmc, W - 1 - s, (int)((chunk >> (s - cb)) & 1), b, n_shared, n_ps));
+    float2* st = state + (size_t)b * row + c.amp0;
+    for (int j = 0; j < (1 << jb); ++j) {
+        float2 Q = P;
+        for (int s = tb; s < cb; ++s)
+            Q = cmul(Q, prefix_v(mats, pmc, W - 1 - s, (j >> (s - tb)) & 1, b, n_shared, n_ps));
+        st[(chunk << cb) | ((int64_t)j << tb) | t] = Q;
+    }
+}
+
+// readout of every circuit: grid (sum of per-circuit chunks, B); 32 doubles per chunk
+__global__ __launch_bounds__(256) void k_expval_part_multi(const DCirc* __restrict__ C, int n_circ,
+                                                           const float2* __restrict__ state,
+                                                           int64_t row, int64_t nchunk_tot,
+                                                           double* __restrict__ part) {
+    __shared__ double red[4][14];
+    int lo = 0, hi = n_circ - 1;
+    const int x = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (C[mid].ic0 <= x) lo = mid; else hi = mid - 1;
+    }
+    const DCirc& c = C[lo];
+    const int W = c.W;
+    const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
+    const int t = threadIdx.x;
+    const int b = blockIdx.y;
+    const int64_t chunk = x - c.ic0;
+    const float2* st = state + (size_t)b * row + c.amp0;
+    float T = 0.f, Sj[4] = {0.f, 0.f, 0.f, 0.f};
+    if (t < (1 << tb)) {
+        for (int j = 0; j < (1 << jb); ++j) {
+            const float2 a = st[(chunk << cb) | ((int64_t)j << tb) | t];
+            const float p = a.x * a.x + a.y * a.y;
+            T += p;
+            for (int i = 0; i < jb; ++i)
+                if ((j >> i) & 1) Sj[i] += p;
+        }
+    }
+    double v[13];
+    v[0] = T;
+    for (int i = 0; i < 4; ++i) v[1 + i] = Sj[i];
+    for (int s = 0; s < 8; ++s) v[5 + s] = ((t >> s) & 1) ? (double)T : 0.0;
+    const int wave = t >> 6, lane = t & 63;
+    for (int k = 0; k < 13; ++k) {
+        const double r = wave_sum(v[k]);
+        if (lane == 0) red[wave][k] = r;
+    }
+    __syncthreads();
+    if (t < W) {
+        auto tot = [&](int k) { return red[0][k] + red[1][k] + red[2][k] + red[3][k]; };
+        const int s = W - 1 - t;
+        const double Tsum = tot(0);
+        double e;
+        if (s < tb) e = Tsum - 2.0 * tot(5 + s);
+        else if (s < cb) e = Tsum - 2.0 * tot(1 + (s - tb));
+        else e = ((chunk >> (s - cb)) & 1) ? -Tsum : Tsum;
+        part[((size_t)b * nchunk_tot + x) * 32 + t] = e;
+    }
+}
+
+// E[b, e0_c + i] = sum over circuit c's chunks; grid (total qubits, B)
+__global__ __launch_bounds__(256) void k_expval_final_multi(const DCirc* __restrict__ C, int n_circ,
+                                                            const double* __restrict__ part,
+                                                            int64_t nchunk_tot, int Wtot,
+                                                            double* __restrict__ out) {
+    __shared__ double red[256];
+    int lo = 0, hi = n_circ - 1;
+    const int col = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (C[mid].e0 <= col) lo = mid; else hi = mid - 1;
+    }
+    const DCirc& c = C[lo];
+    const int i = col - c.e0;
+    const int b = blockIdx.y, t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t k = t; k < c.nchunk; k += 256) s += part[((size_t)b * nchunk_tot + c.ic0 + k) * 32 + i];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[(size_t)b * Wtot + col] = red[0];
 }
 
 // ----------------------------------------------------------------------------
@@ -915,10 +1100,11 @@ namespace {
 
 // ---- profiling: event pairs around launches, per-kernel totals ----
 enum KernelId { K_COEF, K_INIT, K_PASS_FWD, K_PASS_BWD, K_PG_APPLY, K_PG_ADJ, K_ADJ_INIT,
-                K_EXPVAL_PART, K_EXPVAL_FINAL, K_GRAD_REDUCE, K_COUNT };
+                K_EXPVAL_PART, K_EXPVAL_FINAL, K_GRAD_REDUCE, K_MULTI_FWD, K_MULTI_BWD, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {"k_coef", "k_init", "k_pass_fwd", "k_pass_bwd",
                                            "k_pg_apply", "k_pg_adj", "k_adj_init",
-                                           "k_expval_part", "k_expval_final", "k_grad_reduce"};
+                                           "k_expval_part", "k_expval_final", "k_grad_reduce",
+                                           "k_multi_fwd", "k_multi_bwd"};
 
 struct ProfRec {
     int kid;
@@ -976,11 +1162,13 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     const size_t sizes[] = {bytes_of(p->dgates), bytes_of(p->recipes), bytes_of(p->recipe_gates),
                             bytes_of(p->fwd_pass), bytes_of(p->bwd_pass), bytes_of(p->stages),
                             bytes_of(p->ops), bytes_of(p->terms), bytes_of(p->gslot_map),
-                            bytes_of(p->prefix_mat), bytes_of(p->grad_csr)};
+                            bytes_of(p->prefix_mat), bytes_of(p->grad_csr), bytes_of(p->pu),
+                            bytes_of(p->nchv), bytes_of(p->circ)};
     const void* srcs[] = {p->dgates.data(), p->recipes.data(), p->recipe_gates.data(),
                           p->fwd_pass.data(), p->bwd_pass.data(), p->stages.data(),
                           p->ops.data(), p->terms.data(), p->gslot_map.data(),
-                          p->prefix_mat.data(), p->grad_csr.data()};
+                          p->prefix_mat.data(), p->grad_csr.data(), p->pu.data(), p->nchv.data(),
+                          p->circ.data()};
     const int n = (int)(sizeof(sizes) / sizeof(sizes[0]));
     size_t total = 0, offs[16];
     for (int i = 0; i < n; ++i) { offs[i] = total; total += align256(std::max<size_t>(sizes[i], 1)); }
@@ -1015,7 +1203,10 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     t.gslot_map = (int32_t*)(c + offs[8]);
     t.prefix_mat = (int32_t*)(c + offs[9]);
     t.grad_csr = (int32_t*)(c + offs[10]);
-    if (p->opts.method == QSV_METHOD_FUSED && p->opts.codegen &&
+    t.pu = (int64_t*)(c + offs[11]);
+    t.nchv = (int32_t*)(c + offs[12]);
+    t.circ = (DCirc*)(c + offs[13]);
+    if (p->opts.method == QSV_METHOD_FUSED && p->opts.codegen && !p->multi &&
         !(p->fwd_pass.empty() && p->bwd_pass.empty())) {
         JitModules jm;
         std::string err;
@@ -1059,22 +1250,23 @@ size_t mats_bytes(const qsv_plan_t* p, int64_t B) {
     return align256(((size_t)p->n_shared_mats + (size_t)B * p->n_ps_mats) * 8 * sizeof(float) + 32);
 }
 
-int64_t fused_nch(const qsv_plan_t* p) {
-    return int64_t(1) << (p->W - std::min(p->opts.tile_qubits, p->W));
-}
-
-int64_t pg_nch(const qsv_plan_t* p) {
-    const int64_t q = int64_t(1) << std::max(p->W - 2, 0);
-    return std::max<int64_t>(1, q / 1024);
-}
-
 int64_t grad_nch(const qsv_plan_t* p) {
-    return p->opts.method == QSV_METHOD_PER_GATE ? pg_nch(p) : fused_nch(p);
+    return p->opts.method == QSV_METHOD_PER_GATE ? pg_chunks(p->W)
+                                                 : int64_t(1) << (p->W - std::min(p->opts.tile_qubits, p->W));
 }
 
 int64_t expval_nchunk(const qsv_plan_t* p) { return int64_t(1) << (p->W - std::min(p->W, 12)); }
 
-size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * ((size_t)1 << p->W) * 8; }
+// amplitudes of one sample (all circuits of a multi-circuit plan)
+int64_t row_amps(const qsv_plan_t* p) { return p->multi ? p->row : int64_t(1) << p->W; }
+
+size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * (size_t)row_amps(p) * 8; }
+
+size_t partial_bytes(const qsv_plan_t* p, int64_t B) {
+    return align256((size_t)std::max<int64_t>(p->pu_total, 1) * B * sizeof(double));
+}
+
+
 
 int check_plan(const qsv_plan_t* p) {
     if (!p || p->magic != kPlanMagic) {
@@ -1113,9 +1305,73 @@ int run_init(const qsv_plan_t* p, DeviceTables* T, const float* mats, int64_t B,
 int check_batch(const qsv_plan_t* p, int64_t B) {
     if (B <= 0) { set_error("batch must be positive"); return QSV_ERR_ARG; }
     if (B > 65535) { set_error("batch above 65535 is not supported"); return QSV_ERR_ARG; }
-    if ((uint64_t)B > (uint64_t(1) << 40) >> p->W) { set_error("state too large"); return QSV_ERR_TOO_BIG; }
+    if ((uint64_t)B * (uint64_t)row_amps(p) > (uint64_t(1) << 40)) { set_error("state too large"); return QSV_ERR_TOO_BIG; }
+    if (p->multi) {
+        for (const DCirc& c : p->circ)
+            if ((B << (c.W - c.m)) > (int64_t(1) << 30)) { set_error("too many tiles"); return QSV_ERR_TOO_BIG; }
+    }
     return QSV_OK;
 }
+
+// Work lists of the multi-circuit launches for batch B (built once per device
+// and batch size): round r lists every tile of pass r of every circuit that
+// has one, larger circuits first.
+int get_queue(const qsv_plan_t* p, DeviceTables* T, int64_t B, DeviceTables::Queue** out) {
+    std::lock_guard<std::mutex> lk(p->dev_mu);
+    for (auto& q : T->queues)
+        if (q.B == B) { *out = &q; return QSV_OK; }
+    std::vector<int> order(p->circ.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->circ[a].W > p->circ[b].W; });
+    std::vector<DItem> items[2];
+    std::vector<int> rounds[2];
+    for (int dir = 0; dir < 2; ++dir) {
+        int maxp = 0;
+        for (const DCirc& c : p->circ) maxp = std::max(maxp, dir ? c.n_bwd : c.n_fwd);
+        for (int r = 0; r < maxp; ++r) {
+            rounds[dir].push_back((int)items[dir].size());
+            for (int ci : order) {
+                const DCirc& c = p->circ[ci];
+                if (r >= (dir ? c.n_bwd : c.n_fwd)) continue;
+                const int ntiles = (int)(B << (c.W - c.m));
+                for (int t = 0; t < ntiles; ++t) items[dir].push_back({ci, r, t, {0, 0, 0}});
+            }
+        }
+        rounds[dir].push_back((int)items[dir].size());
+    }
+    const size_t b0 = items[0].size() * sizeof(DItem), b1 = items[1].size() * sizeof(DItem);
+    void* d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(align256(b0) + b1, 256)) != hipSuccess) {
+        set_error("hipMalloc of work lists failed");
+        return QSV_ERR_OOM;
+    }
+    if ((b0 && hipMemcpy(d, items[0].data(), b0, hipMemcpyHostToDevice) != hipSuccess) ||
+        (b1 && hipMemcpy((char*)d + align256(b0), items[1].data(), b1, hipMemcpyHostToDevice) != hipSuccess)) {
+        (void)hipFree(d);
+        set_error("hipMemcpy of work lists failed");
+        return QSV_ERR_HIP;
+    }
+    DeviceTables::Queue q;
+    q.B = B;
+    q.fwd = (DItem*)d;
+    q.n_fwd = (int)items[0].size();
+    q.bwd = (DItem*)((char*)d + align256(b0));
+    q.n_bwd = (int)items[1].size();
+    q.mem = d;
+    q.fwd_rounds = rounds[0];
+    q.bwd_rounds = rounds[1];
+    T->queues.push_back(q);
+    *out = &T->queues.back();
+    return QSV_OK;
+}
+
+size_t multi_lds(const qsv_plan_t* p) {
+    int maxg = 0;
+    for (auto& ps : p->bwd_pass) maxg = std::max(maxg, (int)ps.n_gslots);
+    return (size_t(1) << kMaxTileQubitsTables) * 8 + 4 * (size_t)maxg * 8;
+}
+
+
 
 size_t pass_lds_fwd(const qsv_plan_t* p) {
     const int m = std::min(p->opts.tile_qubits, p->W);
@@ -1240,6 +1496,7 @@ void qsv_plan_destroy(qsv_plan_t* p) {
     for (auto& kv : p->dev) {
         if (hipSetDevice(kv.first) == hipSuccess) {
             for (void* m : kv.second.modules) (void)hipModuleUnload((hipModule_t)m);
+            for (auto& q : kv.second.queues) (void)hipFree(q.mem);
             (void)hipFree(kv.second.base);
         }
     }
@@ -1278,6 +1535,8 @@ int qsv_plan_get_info(const qsv_plan_t* p, qsv_plan_info* info) {
     info->n_bwd_stages = p->n_bwd_stages;
     info->n_param_gates = p->n_param;
     info->n_recipes = (int32_t)p->recipes.size();
+    info->n_circuits = p->multi ? (int32_t)p->circ.size() : 1;
+    if (p->multi) info->n_qubits = p->Wtot;
     return QSV_OK;
 }
 
@@ -1302,10 +1561,11 @@ size_t qsv_workspace_size(const qsv_plan_t* p, int64_t B, int32_t op) {
     if (check_plan(p) || B <= 0) return 0;
     switch (op) {
     case QSV_OP_FORWARD: return mats_bytes(p, B);
-    case QSV_OP_EXPVAL: return align256((size_t)B * expval_nchunk(p) * p->W * sizeof(double));
+    case QSV_OP_EXPVAL:
+        if (p->multi) return align256((size_t)B * p->nchunk_tot * 32 * sizeof(double));
+        return align256((size_t)B * expval_nchunk(p) * p->W * sizeof(double));
     case QSV_OP_BACKWARD:
-        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) +
-               align256((size_t)std::max(p->n_param, 1) * B * grad_nch(p) * sizeof(double));
+        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + partial_bytes(p, B);
     default: return 0;
     }
 }
@@ -1324,6 +1584,33 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
     float* mats = (float*)ws;
     float2* st = (float2*)d_state;
     if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
+    if (p->multi) {
+        DeviceTables::Queue* Q;
+        if ((rc = get_queue(p, T, B, &Q))) return rc;
+        const double amps = (double)B * (double)p->row;
+        hipEvent_t ev = prof_begin(p, s);
+        hipLaunchKernelGGL(k_init_multi, dim3((unsigned)p->nchunk_tot, (unsigned)B), dim3(256), 0, s,
+                           (const DCirc*)T->circ, (int)p->circ.size(), st, p->row, T->prefix_mat,
+                           (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+        prof_end(p, s, ev, K_INIT, 8.0 * amps, 0.0);
+        double flops = 0.0, bytes = 0.0;
+        for (const DCirc& c : p->circ)
+            for (int r = 0; r < c.n_fwd; ++r) {
+                flops += p->fwd_pass_flops[c.fwd0 + r] * (double)B * (double)(int64_t(1) << c.W);
+                bytes += 16.0 * (double)B * (double)(int64_t(1) << c.W);
+            }
+        ev = prof_begin(p, s);
+        for (size_t r = 0; r + 1 < Q->fwd_rounds.size(); ++r) {
+            const int i0 = Q->fwd_rounds[r], n = Q->fwd_rounds[r + 1] - i0;
+            hipLaunchKernelGGL(k_multi_fwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
+                               (const DCirc*)T->circ, (const DItem*)(Q->fwd + i0), (const DPass*)T->fwd_pass,
+                               (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
+                               (const float*)mats, p->n_shared_mats, p->n_ps_mats, st, p->row);
+        }
+        prof_end(p, s, ev, K_MULTI_FWD, bytes, flops);
+        HIP_TRY(hipGetLastError());
+        return QSV_OK;
+    }
     if ((rc = run_init(p, T, mats, B, st, s))) return rc;
     const int W = p->W;
     const double amps = (double)B * (double)(int64_t(1) << W);
@@ -1376,6 +1663,24 @@ int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out,
     const size_t need = qsv_workspace_size(p, B, QSV_OP_EXPVAL);
     if (!ws || ws_bytes < need) { set_error("expval workspace too small"); return QSV_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
+    if (p->multi) {
+        DeviceTables* T;
+        if ((rc = get_tables(p, &T))) return rc;
+        double* part = (double*)ws;
+        const double amps = (double)B * (double)p->row;
+        hipEvent_t ev = prof_begin(p, s);
+        hipLaunchKernelGGL(k_expval_part_multi, dim3((unsigned)p->nchunk_tot, (unsigned)B), dim3(256), 0, s,
+                           (const DCirc*)T->circ, (int)p->circ.size(), (const float2*)d_state, p->row,
+                           p->nchunk_tot, part);
+        prof_end(p, s, ev, K_EXPVAL_PART, 8.0 * amps, 3.0 * amps);
+        ev = prof_begin(p, s);
+        hipLaunchKernelGGL(k_expval_final_multi, dim3((unsigned)p->Wtot, (unsigned)B), dim3(256), 0, s,
+                           (const DCirc*)T->circ, (int)p->circ.size(), (const double*)part, p->nchunk_tot,
+                           p->Wtot, out);
+        prof_end(p, s, ev, K_EXPVAL_FINAL, 8.0 * (double)B * p->nchunk_tot * 32, 0.0);
+        HIP_TRY(hipGetLastError());
+        return QSV_OK;
+    }
     const int64_t nchunk = expval_nchunk(p);
     double* part = (double*)ws;
     const double amps = (double)B * (double)(int64_t(1) << p->W);
@@ -1415,10 +1720,33 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     float2* lam = (float2*)c;
     c += align256(state_bytes(p, B));
     double* part = (double*)c;
+    c += partial_bytes(p, B);
     if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
     const int64_t nch = grad_nch(p);
     const double amps = (double)B * (double)(int64_t(1) << W);
-    if (p->opts.method == QSV_METHOD_PER_GATE) {
+    if (p->multi) {
+        DeviceTables::Queue* Q;
+        if ((rc = get_queue(p, T, B, &Q))) return rc;
+        double flops = 0.0, bytes = 0.0;
+        for (const DCirc& cc : p->circ)
+            for (int r = 0; r < cc.n_bwd; ++r) {
+                const int fl = p->bwd_pass[cc.bwd0 + r].flags;
+                const double a = (double)B * (double)(int64_t(1) << cc.W);
+                flops += p->bwd_pass_flops[cc.bwd0 + r] * a;
+                bytes += (((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0)) * a;
+            }
+        hipEvent_t ev = prof_begin(p, s);
+        for (size_t r = 0; r + 1 < Q->bwd_rounds.size(); ++r) {
+            const int i0 = Q->bwd_rounds[r], n = Q->bwd_rounds[r + 1] - i0;
+            hipLaunchKernelGGL(k_multi_bwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
+                               (const DCirc*)T->circ, (const DItem*)(Q->bwd + i0), (const DPass*)T->bwd_pass,
+                               (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
+                               (const int32_t*)T->gslot_map, (const float*)mats, p->n_shared_mats,
+                               p->n_ps_mats, (const float2*)d_state, psi, lam, gout, p->Wtot, p->row, (int)B,
+                               part, (const int64_t*)T->pu);
+        }
+        prof_end(p, s, ev, K_MULTI_BWD, bytes, flops);
+    } else if (p->opts.method == QSV_METHOD_PER_GATE) {
         const int64_t n = B << W;
         hipEvent_t ev = prof_begin(p, s);
         hipLaunchKernelGGL(k_adj_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
@@ -1454,7 +1782,7 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
                 hipLaunchKernelGGL(k_pass_bwd, dim3(tiles), dim3(threads), lds, s, T->bwd_pass + i,
                                    T->stages, T->ops, T->terms, T->gslot_map, (const float*)mats,
                                    p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
-                                   gout, W, (int)B, part);
+                                   gout, W, (int)B, part, (const int64_t*)T->pu);
             }
             prof_end(p, s, ev, K_PASS_BWD, per_amp * amps, p->bwd_pass_flops[i] * amps);
         }
@@ -1463,11 +1791,83 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     if (n_out > 0) {
         hipEvent_t ev = prof_begin(p, s);
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)n_out), dim3(256), 0, s,
-                           (const double*)part, T->grad_csr, p->n_weights, p->n_inputs, (int)B, nch,
-                           gw, gx);
-        prof_end(p, s, ev, K_GRAD_REDUCE, 8.0 * (double)std::max(p->n_param, 1) * B * nch, 0.0);
+                           (const double*)part, T->grad_csr, p->n_weights, p->n_inputs, (int)B,
+                           (const int64_t*)T->pu, (const int32_t*)T->nchv, gw, gx);
+        prof_end(p, s, ev, K_GRAD_REDUCE, 8.0 * (double)std::max<int64_t>(p->pu_total, 1) * B, 0.0);
     }
     HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* opts,
+                   qsv_plan_t** out) {
+    if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
+    *out = nullptr;
+    if (!circuits || n_circuits < 1) { set_error("need at least one circuit"); return QSV_ERR_ARG; }
+    qsv_opts o;
+    qsv_default_opts(&o);
+    if (opts) o = *opts;
+    o.method = QSV_METHOD_FUSED;
+    o.codegen = 0;
+    if (o.fuse_width < 1 || o.fuse_width > 16) { set_error("fuse_width must be in 1..16"); return QSV_ERR_ARG; }
+    if (o.tile_qubits < kRegBits || o.tile_qubits > kMaxTileQubitsTables) { set_error("tile_qubits must be in 4..12"); return QSV_ERR_ARG; }
+    if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
+    if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
+    std::vector<CircuitIn> cs;
+    int64_t row = 0;
+    for (int c = 0; c < n_circuits; ++c) {
+        const qsv_circuit& C = circuits[c];
+        if (C.n_qubits < kRegBits) { set_error("multi-circuit plans need circuits of at least 4 qubits"); return QSV_ERR_ARG; }
+        // validate each circuit like a single plan (host only)
+        qsv_plan_t* tmp = nullptr;
+        qsv_opts ot = o;
+        int rc = qsv_plan(C.n_qubits, C.gates, C.n_gates, C.n_weights, C.n_inputs, &ot, &tmp);
+        if (rc) return rc;
+        qsv_plan_destroy(tmp);
+        row += int64_t(1) << C.n_qubits;
+        cs.push_back({C.n_qubits, C.gates, C.n_gates, C.n_weights, C.n_inputs});
+    }
+    if (row > (int64_t(1) << 34)) { set_error("circuits too large together"); return QSV_ERR_TOO_BIG; }
+    qsv_plan_t* p = new (std::nothrow) qsv_plan_t();
+    if (!p) { set_error("plan allocation failed"); return QSV_ERR_OOM; }
+    p->magic = kPlanMagic;
+    p->opts = o;
+    int W = 0;
+    for (auto& c : cs) W = std::max(W, c.W);
+    p->W = W;
+    int rc;
+    try {
+        rc = build_multi(p, cs);
+    } catch (const std::bad_alloc&) {
+        rc = QSV_ERR_OOM;
+        set_error("out of host memory while planning");
+    }
+    if (rc != QSV_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return QSV_OK;
+}
+
+int qsv_plan_circuit_offsets(const qsv_plan_t* p, int32_t circuit, int64_t* amp, int32_t* qubit,
+                             int32_t* weight, int32_t* input) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    const int n = p->multi ? (int)p->circ.size() : 1;
+    if (circuit < 0 || circuit >= n) { set_error("circuit index out of range"); return QSV_ERR_ARG; }
+    int64_t a = 0;
+    int32_t q = 0, w = 0, x = 0;
+    if (p->multi) {
+        a = p->circ[circuit].amp0;
+        q = p->circ[circuit].e0;
+        w = p->circ_w0[circuit];
+        x = p->circ_x0[circuit];
+    }
+    if (amp) *amp = a;
+    if (qubit) *qubit = q;
+    if (weight) *weight = w;
+    if (input) *input = x;
     return QSV_OK;
 }
 

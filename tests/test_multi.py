@@ -1,0 +1,130 @@
+"""Many circuits in one plan (uneven batch: pass r of every circuit in one launch).
+
+Each circuit's slice of the combined state, expectations and gradients must
+equal the oracle run on that circuit alone.
+"""
+import numpy as np
+import pytest
+
+from paper_2404_09213_amd import binding as B
+from paper_2404_09213_amd import inputs as I
+
+from .helpers import AMP_TOL, EXP_TOL, grad_close
+
+
+def _mixed_set(seed, n, qmin, qmax, with_inputs=True):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        W = int(rng.integers(qmin, qmax + 1))
+        if with_inputs and i % 3 == 0:
+            c = I.rx_ry_rz_cz_ladder(W, int(rng.integers(1, 4)))
+        elif i % 3 == 1:
+            c = I.random_layers(W, int(rng.integers(2, 8)), rng)
+        else:
+            c = I.random_mixed(W, int(rng.integers(20, 90)), rng, n_inputs=2 if with_inputs else 0,
+                               p_input=0.2 if with_inputs else 0.0)
+        out.append(c)
+    return out
+
+
+def _draw(circuits, batch, seed):
+    ws, xs = [], []
+    for i, c in enumerate(circuits):
+        w, x = I.draw_angles(c, batch, seed + i)
+        ws.append(w)
+        xs.append(x.reshape(batch, c.n_inputs))
+    w = np.concatenate(ws) if ws else np.zeros(0, np.float32)
+    x = np.concatenate(xs, axis=1) if any(c.n_inputs for c in circuits) else np.zeros((batch, 0), np.float32)
+    return w.astype(np.float32), x.astype(np.float32), ws, xs
+
+
+# -- host side -------------------------------------------------------------------------
+
+def test_multi_plan_layout_offsets():
+    cs = _mixed_set(1, 7, 4, 9)
+    mp = B.MultiPlan(cs)
+    info = mp.info()
+    assert info["n_circuits"] == 7
+    assert info["n_qubits"] == sum(c.n_qubits for c in cs)
+    assert info["n_weights"] == sum(c.n_weights for c in cs)
+    amp = q = w = x = 0
+    for i, c in enumerate(cs):
+        assert mp.offsets[i] == {"amp": amp, "qubit": q, "weight": w, "input": x}
+        amp += 1 << c.n_qubits
+        q += c.n_qubits
+        w += c.n_weights
+        x += c.n_inputs
+    assert mp.state_len == amp
+
+
+def test_multi_plan_rejects_small_and_invalid():
+    with pytest.raises(B.QsvError):
+        B.MultiPlan([I.rx_ry_rz_cz_ladder(3, 1)])
+    bad = I.rx_ry_rz_cz_ladder(5, 1)
+    bad.gates.append(("CNOT", 2, 2, "none", -1))
+    with pytest.raises(B.QsvError) as e:
+        B.MultiPlan([I.rx_ry_rz_cz_ladder(5, 1), bad])
+    assert e.value.code == -2
+
+
+def test_uneven_set_shape():
+    cs = I.uneven_set(512)
+    ns = [c.n_qubits for c in cs]
+    assert len(cs) == 512 and min(ns) >= 8 and max(ns) <= 18
+    mp = B.MultiPlan(cs)
+    assert mp.state_len == sum(1 << n for n in ns)
+
+
+# -- GPU parity ---------------------------------------------------------------------------
+
+def _run_multi(cs, batch, seed, orc, check_ids=None):
+    import torch
+    dev = torch.device("cuda:0")
+    w, x, ws, xs = _draw(cs, batch, seed)
+    mp = B.MultiPlan(cs)
+    g = np.random.default_rng(seed).uniform(-1, 1, size=(batch, mp.n_out))
+    wt = torch.from_numpy(w).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    print(f"[multi] {len(cs)} circuits: forward", flush=True)
+    st = mp.forward(wt, xt, batch)
+    torch.cuda.synchronize()
+    print("[multi] expval", flush=True)
+    E = mp.expval(st)
+    torch.cuda.synchronize()
+    print("[multi] backward", flush=True)
+    gw, gx = mp.backward(wt, xt, st, torch.from_numpy(g).to(dev))
+    torch.cuda.synchronize()
+    st, E, gw = st.cpu().numpy(), E.cpu().numpy(), gw.cpu().numpy()
+    gx = gx.cpu().numpy() if gx is not None else None
+    ids = range(len(cs)) if check_ids is None else check_ids
+    for i in ids:
+        c, off = cs[i], mp.offsets[i]
+        n = c.n_qubits
+        print(f"[multi] circuit {i}: W={n} gates={len(c.gates)}", flush=True)
+        gi = g[:, off["qubit"]:off["qubit"] + n]
+        rw, rx, rs = orc.adjoint(n, c.gates, ws[i].astype(np.float64), xs[i].astype(np.float64), batch,
+                                 gi, want_state=True)
+        got_st = st[:, off["amp"]:off["amp"] + (1 << n)]
+        assert np.abs(got_st - rs).max() <= AMP_TOL, i
+        assert np.abs(E[:, off["qubit"]:off["qubit"] + n] - orc.expval(n, rs)).max() <= EXP_TOL, i
+        ok, rel = grad_close(gw[off["weight"]:off["weight"] + c.n_weights], rw)
+        assert ok, (i, "weights", rel)
+        if c.n_inputs:
+            ok, rel = grad_close(gx[:, off["input"]:off["input"] + c.n_inputs], rx)
+            assert ok, (i, "inputs", rel)
+
+
+@pytest.mark.gpu
+def test_multi_small_mixed(orc):
+    _run_multi(_mixed_set(11, 9, 4, 13), 2, 11, orc)
+
+
+@pytest.mark.gpu
+def test_multi_uneven_512_sampled(orc):
+    # 512 circuits, 8..18 qubits, 2..12 random layers, batch 1; the oracle
+    # checks a seeded sample of circuits, always including the largest.
+    cs = I.uneven_set(512)
+    rng = np.random.default_rng(1004)
+    ids = sorted(set(rng.choice(512, 6, replace=False).tolist()) | {int(np.argmax([c.n_qubits for c in cs]))})
+    _run_multi(cs, 1, 1004, orc, check_ids=ids)
