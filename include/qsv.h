@@ -82,8 +82,8 @@ enum {
     QSV_METHOD_PER_GATE = 1 /* the plain method: one strided sweep of the state per gate */
 };
 
-/* workspace queries */
-enum { QSV_OP_FORWARD = 0, QSV_OP_EXPVAL = 1, QSV_OP_BACKWARD = 2 };
+/* workspace queries; QSV_OP_STEP = forward + readout + backward (qsv_graph_create) */
+enum { QSV_OP_FORWARD = 0, QSV_OP_EXPVAL = 1, QSV_OP_BACKWARD = 2, QSV_OP_STEP = 3 };
 
 typedef struct {
     int32_t kind;  /* QSV_H ... QSV_CRX */
@@ -265,6 +265,27 @@ typedef struct {
 
 int qsv_profile_enable(qsv_plan_t* plan, int32_t on);
 int qsv_profile_read(qsv_plan_t* plan, qsv_kernel_stat* out, int32_t max_out, int32_t* n_out);
+
+/*
+ * HIP-graph capture of one step: qsv_forward, qsv_expval and (if d_grad_out
+ * is not NULL) qsv_backward with these pointers are recorded once on
+ * `stream` (a non-default hipStream_t) into a graph; qsv_graph_launch then
+ * replays the whole launch sequence with one call. Pointers are fixed in the
+ * graph: to run a new step, write new weights / inputs / upstream gradients
+ * into the same buffers. d_ws must hold qsv_workspace_size(plan, batch,
+ * QSV_OP_STEP) bytes and stay allocated while the graph exists. The plan's
+ * device tables (and generated kernels) are created before capturing, so the
+ * capture itself contains only kernel launches; no memory-set nodes.
+ * Profiling records nothing inside a captured step.
+ */
+typedef struct qsv_graph_s qsv_graph_t;
+
+int qsv_graph_create(const qsv_plan_t* plan, int64_t batch, const float* d_weights,
+                     const float* d_inputs, void* d_state, double* d_expval,
+                     const double* d_grad_out, double* d_grad_weights, double* d_grad_inputs,
+                     void* d_ws, size_t ws_bytes, void* stream, qsv_graph_t** out);
+int qsv_graph_launch(qsv_graph_t* graph, void* stream);
+void qsv_graph_destroy(qsv_graph_t* graph);
 
 const char* qsv_strerror(int code);
 const char* qsv_last_error(void);

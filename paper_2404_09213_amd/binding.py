@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libqsv.so")
 KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "CZ": 8, "CRX": 9}
 SRC = {"none": 0, "weight": 1, "input": 2}
 METHOD = {"fused": 0, "per_gate": 1}
-OP_FORWARD, OP_EXPVAL, OP_BACKWARD = 0, 1, 2
+OP_FORWARD, OP_EXPVAL, OP_BACKWARD, OP_STEP = 0, 1, 2, 3
 
 ERR_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_QUBIT", -3: "QSV_ERR_GATE",
              -4: "QSV_ERR_PARAM", -5: "QSV_ERR_TOO_BIG", -6: "QSV_ERR_OOM", -7: "QSV_ERR_HIP",
@@ -70,7 +70,8 @@ EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_o
            "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
-           "qsv_plan_codegen_check", "qsv_profile_enable",
+           "qsv_plan_codegen_check", "qsv_graph_create", "qsv_graph_launch",
+           "qsv_graph_destroy", "qsv_profile_enable",
            "qsv_profile_read", "qsv_strerror", "qsv_last_error")
 
 _lib = None
@@ -115,6 +116,13 @@ def lib():
         L.qsv_plan_codegen_source.restype = ctypes.c_int
         L.qsv_plan_codegen_check.argtypes = [vp, ctypes.c_char_p]
         L.qsv_plan_codegen_check.restype = ctypes.c_int
+        L.qsv_graph_create.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
+                                       ctypes.POINTER(vp)]
+        L.qsv_graph_create.restype = ctypes.c_int
+        L.qsv_graph_launch.argtypes = [vp, vp]
+        L.qsv_graph_launch.restype = ctypes.c_int
+        L.qsv_graph_destroy.argtypes = [vp]
+        L.qsv_graph_destroy.restype = None
         L.qsv_profile_enable.argtypes = [vp, i32]
         L.qsv_profile_enable.restype = ctypes.c_int
         L.qsv_profile_read.argtypes = [vp, ctypes.POINTER(qsv_kernel_stat), i32,
@@ -235,6 +243,38 @@ def qsv_plan_codegen_source(h):
 
 def qsv_plan_codegen_check(h, arch):
     return _check(lib().qsv_plan_codegen_check(h, arch.encode()))
+
+
+class StepGraph:
+    """A captured step (forward + readout + backward) replayed with one call.
+
+    The buffers passed at capture are fixed: write new angles / upstream
+    gradients into them between replays. Owns its workspace.
+    """
+
+    def __init__(self, plan, weights, inputs, batch, state, expval, grad_out, gw, gx, stream):
+        import torch
+        self.plan = plan
+        n = qsv_workspace_size(plan.handle, batch, OP_STEP)
+        self.ws = torch.empty(max(n, 256), dtype=torch.uint8, device=state.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        P = Plan._ptr
+        _check(lib().qsv_graph_create(plan.handle, int(batch), P(_f32(weights)), P(_f32(inputs)),
+                                      P(state), P(expval), P(grad_out), P(gw), P(gx), P(self.ws),
+                                      self.ws.numel(), ctypes.c_void_p(stream.cuda_stream),
+                                      ctypes.byref(h)))
+        self.handle = h
+        self._keep = (weights, inputs, state, expval, grad_out, gw, gx)
+
+    def launch(self):
+        _check(lib().qsv_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            lib().qsv_graph_destroy(h)
+            self.handle = None
 
 
 def qsv_profile_enable(h, on):

@@ -28,6 +28,7 @@ using namespace qsv;
 // error state
 // ----------------------------------------------------------------------------
 static thread_local std::string g_last_error;
+static thread_local bool g_capturing = false;  // inside qsv_graph_create: no profiling events
 
 namespace qsv {
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -1124,7 +1125,7 @@ Profiler* prof_of(const qsv_plan_t* p) { return static_cast<Profiler*>(p->prof);
 // Returns the start event (or nullptr when profiling is off).
 hipEvent_t prof_begin(const qsv_plan_t* p, hipStream_t s) {
     Profiler* pr = prof_of(p);
-    if (!pr || !pr->on) return nullptr;
+    if (!pr || !pr->on || g_capturing) return nullptr;
     std::lock_guard<std::mutex> lk(pr->mu);
     hipEvent_t e = nullptr;
     if (!pr->pool.empty()) { e = pr->pool.back(); pr->pool.pop_back(); }
@@ -1566,6 +1567,8 @@ size_t qsv_workspace_size(const qsv_plan_t* p, int64_t B, int32_t op) {
         return align256((size_t)B * expval_nchunk(p) * p->W * sizeof(double));
     case QSV_OP_BACKWARD:
         return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + partial_bytes(p, B);
+    case QSV_OP_STEP:
+        return qsv_workspace_size(p, B, QSV_OP_BACKWARD) + qsv_workspace_size(p, B, QSV_OP_EXPVAL);
     default: return 0;
     }
 }
@@ -1869,6 +1872,83 @@ int qsv_plan_circuit_offsets(const qsv_plan_t* p, int32_t circuit, int64_t* amp,
     if (weight) *weight = w;
     if (input) *input = x;
     return QSV_OK;
+}
+
+struct qsv_graph_s {
+    uint32_t magic;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+constexpr uint32_t kGraphMagic = 0x51535647u;  // "QSVG"
+
+int qsv_graph_create(const qsv_plan_t* p, int64_t B, const float* w, const float* x, void* d_state,
+                     double* d_expval, const double* gout, double* gw, double* gx, void* ws,
+                     size_t ws_bytes, void* stream, qsv_graph_t** out) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
+    *out = nullptr;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!stream) { set_error("graph capture needs a non-default stream"); return QSV_ERR_ARG; }
+    if (!d_state || !d_expval || !ws) { set_error("null pointer"); return QSV_ERR_ARG; }
+    if (ws_bytes < qsv_workspace_size(p, B, QSV_OP_STEP)) { set_error("step workspace too small"); return QSV_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    // everything that allocates or copies happens before the capture
+    DeviceTables* T;
+    if ((rc = get_tables(p, &T))) return rc;
+    if (p->multi) {
+        DeviceTables::Queue* Q;
+        if ((rc = get_queue(p, T, B, &Q))) return rc;
+    }
+    const size_t bwd_bytes = qsv_workspace_size(p, B, QSV_OP_BACKWARD);
+    char* wsc = (char*)ws;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    g_capturing = true;
+    rc = qsv_forward(p, w, x, B, d_state, wsc, bwd_bytes, stream);
+    if (!rc) rc = qsv_expval(p, d_state, B, d_expval, wsc + bwd_bytes, ws_bytes - bwd_bytes, stream);
+    if (!rc && gout) rc = qsv_backward(p, w, x, B, d_state, gout, wsc, bwd_bytes, gw, gx, stream);
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (rc || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!rc) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+            rc = QSV_ERR_HIP;
+        }
+        return rc;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        return QSV_ERR_HIP;
+    }
+    qsv_graph_t* g = new (std::nothrow) qsv_graph_t{kGraphMagic, graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        set_error("graph allocation failed");
+        return QSV_ERR_OOM;
+    }
+    *out = g;
+    return QSV_OK;
+}
+
+int qsv_graph_launch(qsv_graph_t* g, void* stream) {
+    if (!g || g->magic != kGraphMagic) { set_error("null or destroyed graph"); return QSV_ERR_HANDLE; }
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return QSV_OK;
+}
+
+void qsv_graph_destroy(qsv_graph_t* g) {
+    if (!g || g->magic != kGraphMagic) return;
+    g->magic = 0;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 int qsv_plan_codegen_source(const qsv_plan_t* p, char* buf, size_t buf_size, size_t* needed) {
