@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--fuse-width", type=int, default=None)
     ap.add_argument("--tile-qubits", type=int, default=None)
     ap.add_argument("--low-qubits", type=int, default=None)
+    ap.add_argument("--uneven-steps", type=int, default=15,
+                    help="timed steps of the 512-circuit uneven set (0 = skip)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: time a plain 1 GiB device copy (counter calibration)")
@@ -104,6 +106,77 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
     stats = plan.profile_read()
     plan.profile(False)
     return total_ms / steps, stats
+
+
+def bench_uneven(args, torch, dev, binding, inputs):
+    """512 circuits of 8..18 qubits and 2..12 random layers, batch 1 each, in
+    one multi-circuit plan: options from the tuner, the whole step (forward +
+    readout + adjoint) replayed as one captured HIP graph. Fresh perturbed
+    weights every step are copied into the captured buffer inside the timed
+    region. Reported beside the main line; not its value."""
+    import numpy as np
+
+    from paper_2404_09213_amd import tune
+    cs = inputs.uneven_set(512, seed=1004)
+    space = {"fuse_width": [1, 2, 3], "tile_qubits": [10, 11, 12], "low_qubits": [3, 4, 5]}
+    tr = tune.tune(cs, 1, multi=True, space=space, top=3, steps=3, log=lambda m: log(args, m))
+    t_plan = time.perf_counter()
+    plan = binding.MultiPlan(cs, **tr["opts"])
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
+    n_runs = args.warmup + args.uneven_steps
+    runs = []
+    for r in range(n_runs):
+        ws = [inputs.draw_angles(c, 1, 1004 + i, run=r + 1)[0] for i, c in enumerate(cs)]
+        runs.append(torch.from_numpy(np.concatenate(ws).astype(np.float32)).to(dev))
+    nw = plan.n_weights
+    wbuf = torch.empty(nw, dtype=torch.float32, device=dev)
+    xbuf = torch.empty((1, 0), dtype=torch.float32, device=dev)
+    state = torch.empty((1, plan.state_len), dtype=torch.complex64, device=dev)
+    E = torch.empty((1, plan.n_out), dtype=torch.float64, device=dev)
+    g = torch.ones((1, plan.n_out), dtype=torch.float64, device=dev)
+    gw = torch.empty(max(nw, 1), dtype=torch.float64, device=dev)
+    gx = torch.empty((1, 1), dtype=torch.float64, device=dev)
+
+    # eager, profiled: algorithmic bytes per step and the per-kernel split
+    eager = [(w, xbuf) for w in runs]
+    ems, stats = run_steps(plan, eager, g, state, E, gw, gx, args.uneven_steps, args.warmup, torch)
+    step_bytes = sum(v["bytes"] for v in stats.values()) / args.uneven_steps
+
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream(device=dev)
+    graph = binding.StepGraph(plan, wbuf, xbuf, 1, state, E, g, gw, gx, stream)
+    with torch.cuda.stream(stream):
+        for r in range(args.warmup):
+            wbuf.copy_(runs[r])
+            graph.launch()
+    stream.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0.record(stream)
+        for r in range(args.warmup, n_runs):
+            wbuf.copy_(runs[r])
+            graph.launch()
+        t1.record(stream)
+    stream.synchronize()
+    gms = t0.elapsed_time(t1) / args.uneven_steps
+    # the last replay against eager calls on the same weights
+    st_e = plan.forward(runs[-1], xbuf, 1)
+    E_e = plan.expval(st_e)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(E_e, E))
+    del graph
+    out = {"circuits": len(cs), "n_qubits": [min(c.n_qubits for c in cs), max(c.n_qubits for c in cs)],
+           "n_gates": sum(len(c.gates) for c in cs), "n_weights": nw,
+           "evals_per_s": round(len(cs) / (gms / 1e3), 1), "ms_per_step": round(gms, 4),
+           "eager_ms_per_step": round(ems, 4),
+           "alg_gbs": round(step_bytes / (gms / 1e3) / 1e9, 1),
+           "opts": tr["opts"], "tune_seconds": tr["seconds"], "plan_ms": round(plan_ms, 1),
+           "graph_equals_eager": same,
+           "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3)}
+                       for k, v in stats.items()}}
+    log(args, f"[bench] uneven: {out}")
+    return out
 
 
 def main():
@@ -175,6 +248,8 @@ def main():
               "launches_per_step": int(sum(v["launches"] for v in pstats.values()) // args.per_gate_steps)}
         log(args, f"[bench] per-gate: {pms:.3f} ms/step  {pg}")
 
+    uneven = bench_uneven(args, torch, dev, binding, inputs) if args.uneven_steps > 0 else None
+
     # roofline of the dominant kernel (largest share of the timed region)
     dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
     gbs = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
@@ -234,6 +309,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "check": check,
+        "uneven": uneven,
     }
     print(json.dumps(out), flush=True)
 

@@ -219,6 +219,16 @@ int qsv_backward(const qsv_plan_t* plan, const float* d_weights, const float* d_
 int qsv_plan_get_info(const qsv_plan_t* plan, qsv_plan_info* info);
 
 /*
+ * Cost model of one step (forward + readout + backward) at this batch, for
+ * choosing fuse_width / tile_qubits / low_qubits without running anything:
+ * each state sweep costs max(algorithmic bytes / hbm_gbs, algorithmic
+ * float32 operations / alu_tflops), each launch adds launch_us.
+ * *us receives the estimate in microseconds. Host only.
+ */
+int qsv_plan_estimate(const qsv_plan_t* plan, int64_t batch, double hbm_gbs, double alu_tflops,
+                      double launch_us, double* us);
+
+/*
  * Gate order in which a forward (which = 0) or backward (which = 1) applies
  * the gates: order[j] is the index of the j-th gate applied (for the
  * backward, the j-th gate uncomputed). Every gate appears once. order has

@@ -70,7 +70,7 @@ EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_o
            "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
-           "qsv_plan_codegen_check", "qsv_graph_create", "qsv_graph_launch",
+           "qsv_plan_codegen_check", "qsv_plan_estimate", "qsv_graph_create", "qsv_graph_launch",
            "qsv_graph_destroy", "qsv_profile_enable",
            "qsv_profile_read", "qsv_strerror", "qsv_last_error")
 
@@ -116,6 +116,9 @@ def lib():
         L.qsv_plan_codegen_source.restype = ctypes.c_int
         L.qsv_plan_codegen_check.argtypes = [vp, ctypes.c_char_p]
         L.qsv_plan_codegen_check.restype = ctypes.c_int
+        L.qsv_plan_estimate.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.qsv_plan_estimate.restype = ctypes.c_int
         L.qsv_graph_create.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
                                        ctypes.POINTER(vp)]
         L.qsv_graph_create.restype = ctypes.c_int
@@ -219,6 +222,13 @@ def qsv_plan_get_info(h):
     info = qsv_plan_info()
     _check(lib().qsv_plan_get_info(h, ctypes.byref(info)))
     return {n: getattr(info, n) for n, _ in qsv_plan_info._fields_}
+
+
+def qsv_plan_estimate(h, batch, hbm_gbs, alu_tflops, launch_us):
+    us = ctypes.c_double()
+    _check(lib().qsv_plan_estimate(h, int(batch), float(hbm_gbs), float(alu_tflops), float(launch_us),
+                                   ctypes.byref(us)))
+    return us.value
 
 
 def qsv_plan_gate_order(h, which, n_gates):

@@ -1951,6 +1951,65 @@ void qsv_graph_destroy(qsv_graph_t* g) {
     delete g;
 }
 
+int qsv_plan_estimate(const qsv_plan_t* p, int64_t B, double hbm_gbs, double alu_tflops,
+                      double launch_us, double* us) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!us || !(hbm_gbs > 0.0) || !(alu_tflops > 0.0) || !(launch_us >= 0.0)) {
+        set_error("estimate: null output or non-positive rate");
+        return QSV_ERR_ARG;
+    }
+    const double bw = hbm_gbs * 1e3;      // bytes per microsecond
+    const double alu = alu_tflops * 1e6;  // operations per microsecond
+    auto sweep = [&](double bytes, double flops) { return std::max(bytes / bw, flops / alu); };
+    double t = 0.0;
+    int64_t launches = 3;  // coefficients, init, readout
+    if (p->multi) {
+        int nf = 0, nb = 0;
+        for (const DCirc& c : p->circ) {
+            const double a = (double)B * (double)(int64_t(1) << c.W);
+            t += sweep(8.0 * a, 0.0) + sweep(8.0 * a, 0.0);  // init + readout
+            for (int r = 0; r < c.n_fwd; ++r) t += sweep(16.0 * a, p->fwd_pass_flops[c.fwd0 + r] * a);
+            for (int r = 0; r < c.n_bwd; ++r) {
+                const int fl = p->bwd_pass[c.bwd0 + r].flags;
+                const double pa = ((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0);
+                t += sweep(pa * a, p->bwd_pass_flops[c.bwd0 + r] * a);
+            }
+            nf = std::max(nf, c.n_fwd);
+            nb = std::max(nb, c.n_bwd);
+        }
+        launches += nf + nb + 2;
+    } else {
+        const double a = (double)B * (double)(int64_t(1) << p->W);
+        t += 2.0 * sweep(8.0 * a, 0.0);  // init + readout
+        if (p->opts.method == QSV_METHOD_PER_GATE) {
+            t += sweep(24.0 * a, 0.0);  // adjoint init
+            for (size_t i = 0; i < p->pg_fwd.size(); ++i) {
+                const PGate& g = p->pg_fwd[i];
+                const double touched = g.cls == OP_SIGN ? 0.25 : (g.cls != OP_DIAG && g.csh >= 0 ? 0.5 : 1.0);
+                t += sweep(16.0 * touched * a, p->pg_fwd_flops[i] * a);
+            }
+            for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
+                const PGate& g = p->pg_bwd[i];
+                const double touched = g.cls == OP_SIGN ? 0.25 : (g.csh >= 0 ? 0.5 : 1.0);
+                t += sweep(32.0 * touched * a, p->pg_bwd_flops[i] * a);
+            }
+            launches += (int64_t)(p->pg_fwd.size() + p->pg_bwd.size()) + 2;
+        } else {
+            for (size_t i = 0; i < p->fwd_pass.size(); ++i) t += sweep(16.0 * a, p->fwd_pass_flops[i] * a);
+            for (size_t i = 0; i < p->bwd_pass.size(); ++i) {
+                const int fl = p->bwd_pass[i].flags;
+                const double pa = ((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0);
+                t += sweep(pa * a, p->bwd_pass_flops[i] * a);
+            }
+            launches += (int64_t)(p->fwd_pass.size() + p->bwd_pass.size()) + 1;
+        }
+    }
+    *us = t + launch_us * (double)launches;
+    return QSV_OK;
+}
+
 int qsv_plan_codegen_source(const qsv_plan_t* p, char* buf, size_t buf_size, size_t* needed) {
     int rc = check_plan(p);
     if (rc) return rc;
