@@ -18,8 +18,10 @@ Prints one JSON line (rank 0, single GPU).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -70,6 +72,41 @@ def copy_calibration(args):
     print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
                       "ms": [round(x, 4) for x in ms],
                       "gbs": round(8 * n / (min(ms) / 1e3) / 1e9, 1)}), flush=True)
+
+
+def family(name):
+    """Per-pass generated kernels (qsv_f<i>, qsv_b<i>) grouped by direction."""
+    if re.fullmatch(r"qsv_f\d+", name):
+        return "pass_fwd(generated)"
+    if re.fullmatch(r"qsv_b\d+", name):
+        return "pass_bwd(generated)"
+    return name
+
+
+def families(stats):
+    out = {}
+    for k, v in stats.items():
+        f = out.setdefault(family(k), {"launches": 0, "total_ms": 0.0, "bytes": 0.0, "flops": 0.0})
+        for key in f:
+            f[key] += v[key]
+    return out
+
+
+def counters_traffic(workload, kernel, sha):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, if it was taken on the same generated source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_counters.md")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+    if not m:
+        return None, "no json block in counter summary"
+    d = json.loads(m.group(1))
+    if d.get("kernel") != kernel:
+        return None, f"counters were taken for {d.get('kernel')}"
+    if d.get("codegen_sha1") != sha:
+        return None, "kernel source changed since the counters were taken"
+    return d["traffic_bytes"], path
 
 
 def log(args, *a):
@@ -222,7 +259,9 @@ def main():
 
     ms, stats = run_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch)
     log(args, f"[bench] fused: {ms:.3f} ms/step")
-    for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_ms"]):
+    fam = families(stats)
+    for k, v in sorted(list(fam.items()) + [kv for kv in stats.items() if family(kv[0]) != kv[0]],
+                       key=lambda kv: -kv[1]["total_ms"]):
         log(args, f"   {k:16s} launches={v['launches']:6d} ms={v['total_ms']:9.3f} "
                   f"GB/s={v['bytes'] / max(v['total_ms'], 1e-9) / 1e6:8.1f} "
                   f"TF/s={v['flops'] / max(v['total_ms'], 1e-9) / 1e9:7.2f}")
@@ -255,6 +294,9 @@ def main():
     gbs = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
     tfs = dom["flops"] / (dom["total_ms"] / 1e3) / 1e12
     hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP32_VECTOR_PEAK_TF
+    sha = hashlib.sha1(binding.qsv_plan_codegen_source(fused.handle).encode()).hexdigest()
+    traffic, traffic_src = counters_traffic(args.workload, dom_name, sha)
+    dfam = fam[family(dom_name)]
     if hbm_frac >= alu_frac:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
@@ -266,7 +308,13 @@ def main():
                  "alg_bytes_per_launch": dom["bytes"] / dom["launches"],
                  "alg_flops_per_launch": dom["flops"] / dom["launches"],
                  "hbm_frac": round(hbm_frac, 4), "alu_frac": round(alu_frac, 4),
-                 "traffic": None})
+                 "alu_frac_nonpacked": round(tfs / (FP32_VECTOR_PEAK_TF / 2), 4),
+                 "family": family(dom_name),
+                 "family_ms_per_step": round(dfam["total_ms"] / args.steps, 4),
+                 "family_alu_tflops": round(dfam["flops"] / (dfam["total_ms"] / 1e3) / 1e12, 3),
+                 "family_hbm_gbs": round(dfam["bytes"] / (dfam["total_ms"] / 1e3) / 1e9, 1),
+                 "traffic": None if traffic is None else round(traffic, 1),
+                 "traffic_source": traffic_src, "codegen_sha1": sha})
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None
@@ -305,7 +353,8 @@ def main():
         "speedup_fused_vs_per_gate": round(pg["ms_per_step"] / ms, 2) if pg else None,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
                         "gbs": round(v["bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
-                    for k, v in stats.items()},
+                    for k, v in list(fam.items()) + [kv for kv in stats.items()
+                                                     if family(kv[0]) != kv[0]]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "check": check,

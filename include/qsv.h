@@ -108,7 +108,12 @@ typedef struct {
     int32_t codegen;     /* fused method: 1 = kernels generated for this plan and
                             compiled with hipRTC on first use on a device (default);
                             0 = table-driven kernels compiled into the library */
-    int32_t reserved[2];
+    int32_t bwd_gate_by_gate; /* 0 (default): in the backward, a chain of 1-qubit
+                            gates on one qubit is uncomputed as one 2x2 product and
+                            its gates' gradients are formed from the X, Y, Z
+                            components taken after the chain, where that costs
+                            fewer operations; 1: every gate is uncomputed on its own */
+    int32_t reserved;
 } qsv_opts;
 
 typedef struct {
@@ -262,7 +267,9 @@ int qsv_plan_codegen_check(const qsv_plan_t* plan, const char* arch);
  *           method's definition of the step, not by the cache hierarchy;
  *   flops = float32 operations of the gate arithmetic (complex multiply = 6).
  * qsv_profile_read waits for the recorded events, writes up to max_out
- * per-kernel totals, sets *n_out, and clears the record. Enabling or reading
+ * per-kernel totals, sets *n_out, and clears the record. Kernels generated
+ * for a plan get one entry per pass under their symbol names ("qsv_f<i>",
+ * "qsv_b<i>"); library kernels one entry per kernel. Enabling or reading
  * while another thread calls into the same plan is not supported.
  */
 typedef struct {

@@ -44,7 +44,7 @@ class qsv_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("fuse_width", ctypes.c_int32),
                 ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
                 ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("bwd_gate_by_gate", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -291,7 +291,7 @@ def qsv_profile_enable(h, on):
     return _check(lib().qsv_profile_enable(h, int(bool(on))))
 
 
-def qsv_profile_read(h, max_out=32):
+def qsv_profile_read(h, max_out=512):
     """Per-kernel totals since the last read: {name: {launches, total_ms, bytes, flops}}."""
     arr = (qsv_kernel_stat * max_out)()
     n = ctypes.c_int32()
@@ -312,8 +312,10 @@ def qsv_last_error():
 # -- plan owner with torch-allocated workspaces -------------------------------------
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
-              max_pass_grads=None, codegen=None):
+              max_pass_grads=None, codegen=None, bwd_gate_by_gate=None):
     o = qsv_default_opts()
+    if bwd_gate_by_gate is not None:
+        o.bwd_gate_by_gate = int(bwd_gate_by_gate)
     if codegen is not None:
         o.codegen = int(codegen)
     o.method = METHOD[method] if isinstance(method, str) else int(method)

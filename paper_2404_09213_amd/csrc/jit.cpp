@@ -124,6 +124,28 @@ __device__ __forceinline__ float qsv_row_sum(float v) {
     v += qsv_dppf<0x140>(v);
     return v;
 }
+// gradient of a gate inside a 1-qubit chain: Im<l|V P V^dagger|psi> from the
+// chain's components cx, cy, cz = Im<l|X|psi>, Im<l|Y|psi>, Im<l|Z|psi>, with
+// V the later gates' product (row-major 2x2) and P = X, Y, Z for axis 0, 1, 2;
+// V P V^dagger = H00 Z + Re(H01) X - Im(H01) Y
+__device__ double qsv_chain_grad(const float* V, int axis, double cx, double cy, double cz) {
+    const double ar = V[0], ai = V[1], br = V[2], bi = V[3], cr = V[4], ci = V[5], dr = V[6], di = V[7];
+    double h00, hr, hi;
+    if (axis == 2) {
+        h00 = ar * ar + ai * ai - br * br - bi * bi;
+        hr = (ar * cr + ai * ci) - (br * dr + bi * di);
+        hi = (ai * cr - ar * ci) - (bi * dr - br * di);
+    } else if (axis == 0) {
+        h00 = 2.0 * (ar * br + ai * bi);
+        hr = (br * cr + bi * ci) + (ar * dr + ai * di);
+        hi = (bi * cr - br * ci) + (ai * dr - ar * di);
+    } else {
+        h00 = -2.0 * (bi * ar - br * ai);
+        hr = -((bi * cr - br * ci) - (ai * dr - ar * di));
+        hi = (br * cr + bi * ci) - (ar * dr + ai * di);
+    }
+    return h00 * cz + hr * cx - hi * cy;
+}
 __device__ __forceinline__ unsigned qsv_sgn(int f, int k) { return ((unsigned)(f >> k) & 1u) << 31; }
 __device__ __forceinline__ f2 qsv_flip(f2 a, unsigned s) {
     return make_float2(__uint_as_float(__float_as_uint(a.x) ^ s), __uint_as_float(__float_as_uint(a.y) ^ s));
@@ -365,10 +387,14 @@ private:
 
     void emit_kernel(const std::string& name) {
         const int tb = W_ - m_;
-        if (bwd_ && ps_->n_gslots) {
-            // parametric-gate ordinal of each gradient slot of this pass
-            o_ << "__device__ const int " << name << "_ord[" << ps_->n_gslots << "] = {";
-            for (int j = 0; j < ps_->n_gslots; ++j) o_ << (j ? "," : "") << p_->gslot_map[ps_->gslot0 + j];
+        if (bwd_ && ps_->n_gout) {
+            // gradient outputs of this pass: ordinal, axis, component slots x/y/z, matrix slot
+            o_ << "__device__ const int " << name << "_out[" << 6 * ps_->n_gout << "] = {";
+            for (int j = 0; j < ps_->n_gout; ++j) {
+                const DGOut& go = p_->gouts[ps_->gout0 + j];
+                o_ << (j ? "," : "") << go.ord << "," << go.axis << "," << go.c0 << "," << go.c1 << ","
+                   << go.c2 << "," << go.mat;
+            }
             o_ << "};\n";
         }
         o_ << "extern \"C\" __global__ void __launch_bounds__(" << threads_ << ") " << name << "(";
@@ -475,11 +501,19 @@ private:
         }
         if (bwd_ && ng) {
             o_ << "  __syncthreads();\n";
-            o_ << "  {\n    const int* ord_ = " << name << "_ord;\n";
+            o_ << "  {\n    __shared__ double cs_[" << ng << "];\n";
             o_ << "    for (int j = t; j < " << ng << "; j += " << threads_ << ") {\n"
                << "      double s = 0.0;\n";
             for (int r = 0; r < nw * 4; ++r) o_ << "      s += (double)red[" << r * ng << " + j];\n";
-            o_ << "      part[((size_t)ord_[j] * B + b) * " << (1u << tb) << "u + tis] = s;\n    }\n  }\n";
+            o_ << "      cs_[j] = s;\n    }\n    __syncthreads();\n";
+            o_ << "    const int* out_ = " << name << "_out;\n"
+               << "    for (int j = t; j < " << ps_->n_gout << "; j += " << threads_ << ") {\n"
+               << "      const int* e = out_ + 6 * j;\n"
+               << "      double v;\n"
+               << "      if (e[1] < 0) v = cs_[e[2]];\n"
+               << "      else v = qsv_chain_grad(e[5] >= 0 ? mats + 8 * (size_t)e[5] : mp + 8 * (size_t)(-e[5] - 1), "
+                  "e[1], e[2] >= 0 ? cs_[e[2]] : 0.0, e[3] >= 0 ? cs_[e[3]] : 0.0, e[4] >= 0 ? cs_[e[4]] : 0.0);\n"
+               << "      part[((size_t)e[0] * B + b) * " << (1u << tb) << "u + tis] = v;\n    }\n  }\n";
         }
         o_ << "}\n\n";
     }

@@ -86,11 +86,28 @@ struct DPass {
     int32_t n_stages;
     int32_t stage0;
     int32_t flags;
-    int32_t n_gslots;     // gradient slots used by this pass
-    int32_t gslot0;       // first entry in gslot_map
-    int32_t pad[2];
+    int32_t n_gslots;     // backward: gradient component slots (one float sum each)
+    int32_t gout0;        // backward: first gradient output (DGOut) of this pass
+    int32_t n_gout;       // backward: gradient outputs of this pass
+    int32_t pad;
     int32_t lq[kMaxQ];    // local tile bit j -> global bit shift (W-1-qubit), j < m
     int32_t oq[kMaxQ];    // tile-index bit k -> global bit shift, k < W-m
+};
+
+// One parametric gate's gradient partial, formed at the end of a backward
+// pass from the pass's component sums c[slot] (slot -1 reads as 0):
+//   axis < 0: value = c[c0]                     (the gate's own Im<l|P|psi>)
+//   axis 0/1/2 (generator X/Y/Z): with V = matrix slot `mat` (the product of
+//   the later gates of the gate's 1-qubit chain) and H = V P V^dagger,
+//   value = H00 c[cz] + Re(H01) c[cx] - Im(H01) c[cy], where c[cx], c[cy],
+//   c[cz] are Im<l|X|psi>, Im<l|Y|psi>, Im<l|Z|psi> on the chain's qubit taken
+//   after the whole chain (c0, c1, c2 = cx, cy, cz).
+struct DGOut {
+    int32_t ord;          // parametric ordinal (partial row)
+    int32_t axis;
+    int32_t c0, c1, c2;
+    int32_t mat;
+    int32_t pad[2];
 };
 
 // Per-gate (plain method) launch description.
@@ -139,7 +156,7 @@ struct DeviceTables {
     DStage* stages = nullptr;
     DOp* ops = nullptr;
     DTerm* terms = nullptr;
-    int32_t* gslot_map = nullptr;
+    DGOut* gouts = nullptr;
     int32_t* prefix_mat = nullptr;
     int32_t* grad_csr = nullptr;   // weights then inputs: offsets, then slot lists
     int64_t* pu = nullptr;         // per parametric ordinal: partial offset in units of B
@@ -186,7 +203,7 @@ struct qsv_plan_s {
     std::vector<qsv::DStage> stages;
     std::vector<qsv::DOp> ops;
     std::vector<qsv::DTerm> terms;
-    std::vector<int32_t> gslot_map;     // local gradient slot -> parametric ordinal
+    std::vector<qsv::DGOut> gouts;      // backward gradient outputs (per pass ranges)
 
     // per-gate schedule
     std::vector<qsv::PGate> pg_fwd, pg_bwd;

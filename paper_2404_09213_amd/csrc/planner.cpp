@@ -212,7 +212,38 @@ struct Unit {
     std::vector<int> gates;  // in application order
     uint32_t D = 0, C = 0;
     int qubit = -1;          // chain qubit, or target of a 2-qubit gate
+    int comps = 0;           // backward chain: Pauli components needed (bit 0 X, 1 Y, 2 Z)
 };
+
+// Generator axis of a parametric gate (0 X, 1 Y, 2 Z).
+int axis_of(int kind) { return kind == QSV_RY ? 1 : kind == QSV_RZ ? 2 : 0; }
+
+// Pauli support (bit 0 X, 1 Y, 2 Z) of U P U^dagger for P spanned by the
+// Paulis in `s`, with U one 1-qubit gate: a rotation about one axis keeps that
+// axis and mixes the other two; H swaps X and Z; X, Y, Z only change signs.
+int conj_support(int kind, int s) {
+    int out = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (!(s >> a & 1)) continue;
+        switch (kind) {
+        case QSV_RX: out |= a == 0 ? 1 : 6; break;
+        case QSV_RY: out |= a == 1 ? 2 : 5; break;
+        case QSV_RZ: out |= a == 2 ? 4 : 3; break;
+        case QSV_H: out |= a == 0 ? 4 : a == 2 ? 1 : 2; break;
+        default: out |= 1 << a; break;
+        }
+    }
+    return out;
+}
+
+// Vector instructions per amplitude pair and state array of one apply op.
+int apply_cost(int cls) {
+    switch (cls) {
+    case OP_U2: return 16;
+    case OP_SWAP: return 1;
+    default: return 8;
+    }
+}
 
 std::vector<Unit> fwd_units(const qsv_plan_t* p, const std::vector<int>& gates) {
     std::vector<Unit> units;
@@ -244,15 +275,79 @@ std::vector<Unit> fwd_units(const qsv_plan_t* p, const std::vector<int>& gates) 
     return units;
 }
 
-std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates) {
-    std::vector<Unit> units;
+// Backward units, in uncompute order. A run of 1-qubit gates on one qubit
+// (with only gates on other qubits in between) becomes one chain unit when
+// uncomputing it as a single 2x2 product, with the gradients recovered from
+// the chain's X/Y/Z components, takes fewer vector operations than gate by
+// gate (and needs no more gradient slots); otherwise every gate is its own
+// unit. The gradient of gate j of a chain U_n...U_1 is
+// Im<l|V_j P_j V_j^dagger|psi> with V_j = U_n...U_{j+1}, taken after the
+// chain: a combination of Im<l|X|psi>, Im<l|Y|psi>, Im<l|Z|psi>.
+std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates, bool fuse) {
+    std::vector<Unit> chains;
+    std::vector<int> open(p->W, -1);
     for (auto it = gates.rbegin(); it != gates.rend(); ++it) {
-        Unit x;
-        x.gates.push_back(*it);
-        gate_sets(p->gates[*it], x.D, x.C);
-        const qsv_gate& G = p->gates[*it];
-        x.qubit = is_two(G.kind) ? G.q1 : G.q0;
-        units.push_back(x);
+        const int g = *it;
+        const qsv_gate& G = p->gates[g];
+        uint32_t D, C;
+        gate_sets(G, D, C);
+        if (!is_two(G.kind)) {
+            int& u = open[G.q0];
+            if (u < 0) {
+                chains.emplace_back();
+                u = (int)chains.size() - 1;
+                chains[u].qubit = G.q0;
+            }
+            chains[u].gates.insert(chains[u].gates.begin(), g);
+            chains[u].D |= D;
+            chains[u].C |= C;
+        } else {
+            open[G.q0] = open[G.q1] = -1;
+            Unit x;
+            x.gates.push_back(g);
+            x.D = D;
+            x.C = C;
+            x.qubit = G.q1;
+            chains.push_back(x);
+        }
+    }
+    std::vector<Unit> units;
+    for (Unit& u : chains) {
+        u.C &= ~u.D;
+        const int n = (int)u.gates.size();
+        bool fused = false;
+        if (fuse && n >= 2 && !is_two(p->gates[u.gates[0]].kind)) {
+            int comps = 0, nparam = 0, sep = 0;
+            for (int j = 0; j < n; ++j) {
+                const qsv_gate& G = p->gates[u.gates[j]];
+                sep += 2 * apply_cost(recipe_class(p, {u.gates[j]}));
+                if (G.src == QSV_SRC_NONE) continue;
+                ++nparam;
+                sep += 4;
+                int sup = 1 << axis_of(G.kind);
+                for (int k = j + 1; k < n; ++k) sup = conj_support(p->gates[u.gates[k]].kind, sup);
+                comps |= sup;
+            }
+            const int ncomp = popc((uint32_t)comps);
+            const int cost = 2 * apply_cost(recipe_class(p, u.gates)) + 4 * ncomp;
+            if (cost < sep && ncomp <= std::max(nparam, 1)) {
+                fused = true;
+                u.comps = comps;
+            }
+        }
+        if (fused) {
+            units.push_back(u);
+            continue;
+        }
+        for (int j = n - 1; j >= 0; --j) {
+            Unit x;
+            x.gates.push_back(u.gates[j]);
+            const qsv_gate& G = p->gates[u.gates[j]];
+            gate_sets(G, x.D, x.C);
+            x.C &= ~x.D;
+            x.qubit = is_two(G.kind) ? G.q1 : G.q0;
+            units.push_back(x);
+        }
     }
     return units;
 }
@@ -304,11 +399,12 @@ struct PassBuilder {
             if (tile >> q & 1) { local_of_qubit[q] = j; ps.lq[j++] = W - 1 - q; }
             else { local_of_qubit[q] = -1; ps.oq[k++] = W - 1 - q; }
         }
-        std::vector<Unit> units = backward ? bwd_units(p, gates) : fwd_units(p, gates);
+        std::vector<Unit> units = backward ? bwd_units(p, gates, !p->opts.bwd_gate_by_gate)
+                                           : fwd_units(p, gates);
         auto groups = group_stages(units);
         ps.stage0 = (int32_t)p->stages.size();
         ps.n_stages = (int32_t)groups.size();
-        ps.gslot0 = (int32_t)p->gslot_map.size();
+        ps.gout0 = (int32_t)p->gouts.size();
         int nslot = 0;
         for (auto& grp : groups) {
             DStage st;
@@ -331,7 +427,8 @@ struct PassBuilder {
             int sign_op = -1;  // open OP_SIGN being extended
             for (int ui : grp.second) {
                 const Unit& U = units[ui];
-                for (int g : U.gates) order.push_back(g);
+                if (backward) order.insert(order.end(), U.gates.rbegin(), U.gates.rend());
+                else order.insert(order.end(), U.gates.begin(), U.gates.end());
                 const qsv_gate& G = p->gates[U.gates[0]];
                 const bool is_cz = U.gates.size() == 1 && G.kind == QSV_CZ;
                 if (is_cz) {
@@ -374,7 +471,45 @@ struct PassBuilder {
                     continue;
                 }
                 sign_op = -1;
-                if (backward) {
+                auto comp_op = [&](int kind) {
+                    DOp o;
+                    std::memset(&o, 0, sizeof o);
+                    o.kind = kind;
+                    o.pos = pos_of(U.qubit);
+                    o.sh = W - 1 - U.qubit;
+                    o.ctl = -1;
+                    o.slot = nslot++;
+                    p->ops.push_back(o);
+                    return o.slot;
+                };
+                if (backward && U.comps) {
+                    // chain: X/Y/Z components after the chain, one output per
+                    // parametric gate, then the chain's product uncomputed at once
+                    int slot_of[3] = {-1, -1, -1};
+                    for (int a = 0; a < 3; ++a)
+                        if (U.comps >> a & 1) slot_of[a] = comp_op(OP_GX + a);
+                    const int n = (int)U.gates.size();
+                    for (int j = 0; j < n; ++j) {
+                        const qsv_gate& Gj = p->gates[U.gates[j]];
+                        if (Gj.src == QSV_SRC_NONE) continue;
+                        DGOut go;
+                        std::memset(&go, 0, sizeof go);
+                        go.ord = p->param_ordinal[U.gates[j]];
+                        if (j == n - 1) {
+                            go.axis = -1;
+                            go.c0 = slot_of[axis_of(Gj.kind)];
+                            go.c1 = go.c2 = -1;
+                        } else {
+                            go.axis = axis_of(Gj.kind);
+                            go.c0 = slot_of[0];
+                            go.c1 = slot_of[1];
+                            go.c2 = slot_of[2];
+                            go.mat = add_recipe(p, std::vector<int>(U.gates.begin() + j + 1, U.gates.end()),
+                                                false);
+                        }
+                        p->gouts.push_back(go);
+                    }
+                } else if (backward) {
                     // gradient partial (before uncomputing the gate), then U^dagger
                     const int g = U.gates[0];
                     if (G.src != QSV_SRC_NONE) {
@@ -390,8 +525,14 @@ struct PassBuilder {
                         }
                         o.mat = 0;
                         o.slot = nslot++;
-                        p->gslot_map.push_back(p->param_ordinal[g]);
                         p->ops.push_back(o);
+                        DGOut go;
+                        std::memset(&go, 0, sizeof go);
+                        go.ord = p->param_ordinal[g];
+                        go.axis = -1;
+                        go.c0 = o.slot;
+                        go.c1 = go.c2 = -1;
+                        p->gouts.push_back(go);
                     }
                 }
                 DOp o;
@@ -412,6 +553,7 @@ struct PassBuilder {
             p->stages.push_back(st);
         }
         ps.n_gslots = nslot;
+        ps.n_gout = (int32_t)p->gouts.size() - ps.gout0;
         out.push_back(ps);
     }
 };
@@ -572,10 +714,11 @@ int build_plan(qsv_plan_t* p) {
     const int m = std::min(o.tile_qubits, W);
     const int c = std::min(o.low_qubits, m - 1);
     // LDS budget for gradient partials per slot: float32 per 16-lane row
-    // (generated kernels) or float64 per wave (table-driven) = threads / 4 bytes
+    // (generated kernels) or float64 per wave (table-driven) = threads / 4
+    // bytes, plus one float64 component sum; 256 bytes kept for the rest
     const int threads = std::max(64, 1 << (m - kRegBits));
     const int exch = (1 << m) * 8;
-    int max_grads = std::min(o.max_pass_grads, (160 * 1024 - exch) / (threads / 4));
+    int max_grads = std::min(o.max_pass_grads, (160 * 1024 - 256 - exch) / (threads / 4 + 8));
     max_grads = std::max(max_grads, 1);
     {
         std::vector<uint32_t> dense;
@@ -650,7 +793,7 @@ int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs) {
         d.nchunk = 1 << (ci.W - std::min(ci.W, 12));
         const int g0 = (int)p->dgates.size(), rg0 = (int)p->recipe_gates.size();
         const int st0 = (int)p->stages.size(), op0 = (int)p->ops.size(), t0 = (int)p->terms.size();
-        const int gs0 = (int)p->gslot_map.size();
+        const int go0 = (int)p->gouts.size();
         const int sh0 = p->n_shared_mats, ps0 = p->n_ps_mats;
         auto fix_mat = [&](int32_t mat) { return mat >= 0 ? mat + sh0 : -((-mat - 1) + ps0) - 1; };
         for (DGate g : sub.dgates) {
@@ -678,15 +821,18 @@ int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs) {
             p->ops.push_back(o);
         }
         p->terms.insert(p->terms.end(), sub.terms.begin(), sub.terms.end());
-        for (int32_t o : sub.gslot_map) p->gslot_map.push_back(o + ord0);
+        for (DGOut o : sub.gouts) {
+            o.ord += ord0;
+            if (o.axis >= 0) o.mat = fix_mat(o.mat);
+            p->gouts.push_back(o);
+        }
         for (DPass ps : sub.fwd_pass) {
             ps.stage0 += st0;
-            ps.gslot0 += gs0;
             p->fwd_pass.push_back(ps);
         }
         for (DPass ps : sub.bwd_pass) {
             ps.stage0 += st0;
-            ps.gslot0 += gs0;
+            ps.gout0 += go0;
             p->bwd_pass.push_back(ps);
         }
         p->fwd_pass_flops.insert(p->fwd_pass_flops.end(), sub.fwd_pass_flops.begin(), sub.fwd_pass_flops.end());

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 
@@ -807,9 +808,36 @@ __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
 // gradient slot j goes to part[B * pu[ord] + b * nch + tis] with ord its
 // parametric-gate ordinal. lds: 2^m float2 followed by (blockDim/64) x
 // n_gslots doubles.
+// Gradient of a gate inside a 1-qubit chain from the chain's components
+// cx, cy, cz = Im<l|X|psi>, Im<l|Y|psi>, Im<l|Z|psi> taken after the chain:
+// Im<l|H|psi> with H = V P V^dagger, V = the later gates' product (row-major
+// 2x2, interleaved re/im), P the gate's generator (axis 0 X, 1 Y, 2 Z).
+// H is traceless Hermitian, H = H00 Z + Re(H01) X - Im(H01) Y.
+__device__ double chain_grad(const float* V, int axis, double cx, double cy, double cz) {
+    const double ar = V[0], ai = V[1], br = V[2], bi = V[3];  // v00, v01
+    const double cr = V[4], ci = V[5], dr = V[6], di = V[7];  // v10, v11
+    double h00, hr, hi;
+    if (axis == 2) {         // V Z V^dagger
+        h00 = ar * ar + ai * ai - br * br - bi * bi;
+        hr = (ar * cr + ai * ci) - (br * dr + bi * di);   // v00 conj(v10) - v01 conj(v11)
+        hi = (ai * cr - ar * ci) - (bi * dr - br * di);
+    } else if (axis == 0) {  // V X V^dagger
+        h00 = 2.0 * (ar * br + ai * bi);                  // 2 Re(v00 conj(v01))
+        hr = (br * cr + bi * ci) + (ar * dr + ai * di);   // v01 conj(v10) + v00 conj(v11)
+        hi = (bi * cr - br * ci) + (ai * dr - ar * di);
+    } else {                 // V Y V^dagger
+        h00 = -2.0 * (bi * ar - br * ai);                 // -2 Im(v01 conj(v00))
+        const double ur = (br * cr + bi * ci) - (ar * dr + ai * di);  // v01 conj(v10) - v00 conj(v11)
+        const double ui = (bi * cr - br * ci) - (ai * dr - ar * di);
+        hr = -ui;                                          // i (ur + i ui)
+        hi = ur;
+    }
+    return h00 * cz + hr * cx - hi * cy;
+}
+
 __device__ __forceinline__ void pass_bwd_tile(
     const DPass* __restrict__ P, const DStage* __restrict__ S, const DOp* __restrict__ O,
-    const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
+    const DTerm* __restrict__ Tm, const DGOut* __restrict__ gouts,
     const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN_s,
     float2* __restrict__ psi_s, float2* __restrict__ lam_s, const double* __restrict__ g, int W,
     int64_t B, int b, int64_t tis, double* __restrict__ part, const int64_t* __restrict__ pu,
@@ -905,10 +933,24 @@ __device__ __forceinline__ void pass_bwd_tile(
     __syncthreads();
     const int ng = P->n_gslots;
     const int64_t nch = int64_t(1) << tbits;
+    // component sums (wave 0's entry of slot j is only touched by thread j)
     for (int j = t; j < ng; j += blockDim.x) {
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w) s += red[w * ng + j];
-        part[B * pu[gslot_map[P->gslot0 + j]] + (int64_t)b * nch + tis] = s;
+        red[j] = s;
+    }
+    __syncthreads();
+    for (int j = t; j < P->n_gout; j += blockDim.x) {
+        const DGOut o = gouts[P->gout0 + j];
+        double v;
+        if (o.axis < 0) {
+            v = red[o.c0];
+        } else {
+            const double cx = o.c0 >= 0 ? red[o.c0] : 0.0, cy = o.c1 >= 0 ? red[o.c1] : 0.0,
+                         cz = o.c2 >= 0 ? red[o.c2] : 0.0;
+            v = chain_grad(mat_ptr(mats, o.mat, b, n_shared, n_ps), o.axis, cx, cy, cz);
+        }
+        part[B * pu[o.ord] + (int64_t)b * nch + tis] = v;
     }
     __syncthreads();  // red and lds may be reused by the caller's next tile
 }
@@ -929,7 +971,7 @@ __global__ __launch_bounds__(1024) void k_pass_fwd(const DPass* __restrict__ P,
 
 __global__ __launch_bounds__(256) void k_pass_bwd(
     const DPass* __restrict__ P, const DStage* __restrict__ S, const DOp* __restrict__ O,
-    const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
+    const DTerm* __restrict__ Tm, const DGOut* __restrict__ gouts,
     const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
     float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int W,
     int B, double* __restrict__ part, const int64_t* __restrict__ pu) {
@@ -939,7 +981,7 @@ __global__ __launch_bounds__(256) void k_pass_bwd(
     const int b = (int)(tile >> tbits);
     const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
     const size_t off = (size_t)b << W;
-    pass_bwd_tile(P, S, O, Tm, gslot_map, mats, n_shared, n_ps, psiN + off, psi + off, lam + off,
+    pass_bwd_tile(P, S, O, Tm, gouts, mats, n_shared, n_ps, psiN + off, psi + off, lam + off,
                   gout + (size_t)b * W, W, B, b, tis, part, pu, lds);
 }
 
@@ -968,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_multi_fwd(
 __global__ __launch_bounds__(256) void k_multi_bwd(
     const DCirc* __restrict__ C, const DItem* __restrict__ Q,
     const DPass* __restrict__ passes, const DStage* __restrict__ S, const DOp* __restrict__ O,
-    const DTerm* __restrict__ Tm, const int32_t* __restrict__ gslot_map,
+    const DTerm* __restrict__ Tm, const DGOut* __restrict__ gouts,
     const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
     float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int Wtot,
     int64_t row, int B, double* __restrict__ part, const int64_t* __restrict__ pu) {
@@ -979,7 +1021,7 @@ __global__ __launch_bounds__(256) void k_multi_bwd(
     const int b = I.tile >> tbits;
     const int64_t tis = I.tile & ((1 << tbits) - 1);
     const size_t off = (size_t)b * row + c.amp0;
-    pass_bwd_tile(passes + c.bwd0 + I.pass, S, O, Tm, gslot_map, mats, n_shared, n_ps, psiN + off,
+    pass_bwd_tile(passes + c.bwd0 + I.pass, S, O, Tm, gouts, mats, n_shared, n_ps, psiN + off,
                   psi + off, lam + off, gout + (size_t)b * Wtot + c.e0, c.W, B, b, tis, part, pu, lds);
 }
 
@@ -1109,6 +1151,7 @@ const char* const kKernelNames[K_COUNT] = {"k_coef", "k_init", "k_pass_fwd", "k_
 
 struct ProfRec {
     int kid;
+    int sub;  // pass index of a generated per-pass kernel, else -1
     hipEvent_t a, b;
     double bytes, flops;
 };
@@ -1134,7 +1177,8 @@ hipEvent_t prof_begin(const qsv_plan_t* p, hipStream_t s) {
     return e;
 }
 
-void prof_end(const qsv_plan_t* p, hipStream_t s, hipEvent_t a, int kid, double bytes, double flops) {
+void prof_end(const qsv_plan_t* p, hipStream_t s, hipEvent_t a, int kid, double bytes, double flops,
+              int sub = -1) {
     if (!a) return;
     Profiler* pr = prof_of(p);
     std::lock_guard<std::mutex> lk(pr->mu);
@@ -1142,7 +1186,7 @@ void prof_end(const qsv_plan_t* p, hipStream_t s, hipEvent_t a, int kid, double 
     if (!pr->pool.empty()) { b = pr->pool.back(); pr->pool.pop_back(); }
     else if (hipEventCreate(&b) != hipSuccess) { pr->pool.push_back(a); return; }
     (void)hipEventRecord(b, s);
-    pr->recs.push_back({kid, a, b, bytes, flops});
+    pr->recs.push_back({kid, sub, a, b, bytes, flops});
 }
 
 template <class T>
@@ -1162,12 +1206,12 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     DeviceTables t;
     const size_t sizes[] = {bytes_of(p->dgates), bytes_of(p->recipes), bytes_of(p->recipe_gates),
                             bytes_of(p->fwd_pass), bytes_of(p->bwd_pass), bytes_of(p->stages),
-                            bytes_of(p->ops), bytes_of(p->terms), bytes_of(p->gslot_map),
+                            bytes_of(p->ops), bytes_of(p->terms), bytes_of(p->gouts),
                             bytes_of(p->prefix_mat), bytes_of(p->grad_csr), bytes_of(p->pu),
                             bytes_of(p->nchv), bytes_of(p->circ)};
     const void* srcs[] = {p->dgates.data(), p->recipes.data(), p->recipe_gates.data(),
                           p->fwd_pass.data(), p->bwd_pass.data(), p->stages.data(),
-                          p->ops.data(), p->terms.data(), p->gslot_map.data(),
+                          p->ops.data(), p->terms.data(), p->gouts.data(),
                           p->prefix_mat.data(), p->grad_csr.data(), p->pu.data(), p->nchv.data(),
                           p->circ.data()};
     const int n = (int)(sizeof(sizes) / sizeof(sizes[0]));
@@ -1201,7 +1245,7 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     t.stages = (DStage*)(c + offs[5]);
     t.ops = (DOp*)(c + offs[6]);
     t.terms = (DTerm*)(c + offs[7]);
-    t.gslot_map = (int32_t*)(c + offs[8]);
+    t.gouts = (DGOut*)(c + offs[8]);
     t.prefix_mat = (int32_t*)(c + offs[9]);
     t.grad_csr = (int32_t*)(c + offs[10]);
     t.pu = (int64_t*)(c + offs[11]);
@@ -1440,6 +1484,7 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.codegen == 0 && o.tile_qubits > kMaxTileQubitsTables) { set_error("table-driven kernels (codegen 0) need tile_qubits <= 12"); return QSV_ERR_ARG; }
     if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
+    if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
@@ -1651,7 +1696,8 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
                                T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
                                p->n_ps_mats, st, W);
         }
-        prof_end(p, s, ev, K_PASS_FWD, 16.0 * amps, p->fwd_pass_flops[i] * amps);
+        prof_end(p, s, ev, K_PASS_FWD, 16.0 * amps, p->fwd_pass_flops[i] * amps,
+                 T->fwd_fn.empty() ? -1 : (int)i);
     }
     HIP_TRY(hipGetLastError());
     return QSV_OK;
@@ -1744,7 +1790,7 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
             hipLaunchKernelGGL(k_multi_bwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
                                (const DCirc*)T->circ, (const DItem*)(Q->bwd + i0), (const DPass*)T->bwd_pass,
                                (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
-                               (const int32_t*)T->gslot_map, (const float*)mats, p->n_shared_mats,
+                               (const DGOut*)T->gouts, (const float*)mats, p->n_shared_mats,
                                p->n_ps_mats, (const float2*)d_state, psi, lam, gout, p->Wtot, p->row, (int)B,
                                part, (const int64_t*)T->pu);
         }
@@ -1783,11 +1829,12 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
                                               s, args, nullptr));
             } else {
                 hipLaunchKernelGGL(k_pass_bwd, dim3(tiles), dim3(threads), lds, s, T->bwd_pass + i,
-                                   T->stages, T->ops, T->terms, T->gslot_map, (const float*)mats,
+                                   T->stages, T->ops, T->terms, T->gouts, (const float*)mats,
                                    p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
                                    gout, W, (int)B, part, (const int64_t*)T->pu);
             }
-            prof_end(p, s, ev, K_PASS_BWD, per_amp * amps, p->bwd_pass_flops[i] * amps);
+            prof_end(p, s, ev, K_PASS_BWD, per_amp * amps, p->bwd_pass_flops[i] * amps,
+                     T->bwd_fn.empty() ? -1 : (int)i);
         }
     }
     const int n_out = p->n_weights + (gx ? (int)B * p->n_inputs : 0);
@@ -1816,6 +1863,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.tile_qubits < kRegBits || o.tile_qubits > kMaxTileQubitsTables) { set_error("tile_qubits must be in 4..12"); return QSV_ERR_ARG; }
     if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
+    if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
     std::vector<CircuitIn> cs;
     int64_t row = 0;
     for (int c = 0; c < n_circuits; ++c) {
@@ -2053,8 +2101,8 @@ int qsv_profile_read(qsv_plan_t* p, qsv_kernel_stat* out, int32_t max_out, int32
     int rc = check_plan(p);
     if (rc) return rc;
     if (!n_out || (max_out > 0 && !out)) { set_error("null pointer"); return QSV_ERR_ARG; }
-    qsv_kernel_stat tot[K_COUNT];
-    std::memset(tot, 0, sizeof tot);
+    // totals per (kernel, generated pass); ordered by kernel id, then pass
+    std::map<std::pair<int, int>, qsv_kernel_stat> tot;
     Profiler* pr = prof_of(p);
     int err = QSV_OK;
     if (pr) {
@@ -2065,22 +2113,28 @@ int qsv_profile_read(qsv_plan_t* p, qsv_kernel_stat* out, int32_t max_out, int32
                 set_error("event timing failed");
                 err = QSV_ERR_HIP;
             }
-            tot[r.kid].launches++;
-            tot[r.kid].total_ms += ms;
-            tot[r.kid].bytes += r.bytes;
-            tot[r.kid].flops += r.flops;
+            auto it = tot.find({r.kid, r.sub});
+            if (it == tot.end()) {
+                qsv_kernel_stat z;
+                std::memset(&z, 0, sizeof z);
+                if (r.sub >= 0)  // the generated kernel's own symbol name
+                    std::snprintf(z.name, sizeof z.name, "qsv_%c%d", r.kid == K_PASS_FWD ? 'f' : 'b', r.sub);
+                else
+                    std::snprintf(z.name, sizeof z.name, "%s", kKernelNames[r.kid]);
+                it = tot.emplace(std::make_pair(r.kid, r.sub), z).first;
+            }
+            it->second.launches++;
+            it->second.total_ms += ms;
+            it->second.bytes += r.bytes;
+            it->second.flops += r.flops;
             pr->pool.push_back(r.a);
             pr->pool.push_back(r.b);
         }
         pr->recs.clear();
     }
     int n = 0;
-    for (int k = 0; k < K_COUNT; ++k) {
-        if (!tot[k].launches) continue;
-        if (n < max_out) {
-            out[n] = tot[k];
-            std::snprintf(out[n].name, sizeof out[n].name, "%s", kKernelNames[k]);
-        }
+    for (auto& kv : tot) {
+        if (n < max_out) out[n] = kv.second;
         ++n;
     }
     *n_out = std::min(n, max_out);

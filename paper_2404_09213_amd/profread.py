@@ -1,0 +1,99 @@
+"""Summaries of rocprofv3 CSV output (`-f csv`) for this library's kernels.
+
+    python -m paper_2404_09213_amd.profread stats DIR
+        per-kernel calls / total / average duration from *kernel_stats.csv
+    python -m paper_2404_09213_amd.profread counters DIR [KERNEL_REGEX]
+        per-kernel mean counter value per dispatch from *counter_collection.csv
+    python -m paper_2404_09213_amd.profread traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR \\
+            COPY_WRITE_DIR COPY_BYTES KERNEL
+        HBM bytes per dispatch of KERNEL from FETCH_SIZE / WRITE_SIZE (KiB per
+        dispatch), each scaled by what the same counter reads for a plain
+        device copy of COPY_BYTES bytes read and written; prints JSON
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import json
+import os
+import re
+import sys
+
+
+def _one(d, suffix):
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def short(name):
+    """Kernel name without its argument list."""
+    return name.split("(")[0].strip()
+
+
+def kernel_stats(d):
+    rows = []
+    with open(_one(d, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append({"name": short(r["Name"]), "calls": int(r["Calls"]),
+                         "total_us": float(r["TotalDurationNs"]) / 1e3,
+                         "avg_us": float(r["AverageNs"]) / 1e3,
+                         "percent": float(r["Percentage"])})
+    return rows
+
+
+def counter_means(d, kernel_regex=None):
+    """{(kernel, counter): (dispatches, mean value per dispatch)}"""
+    agg = collections.defaultdict(list)
+    rx = re.compile(kernel_regex) if kernel_regex else None
+    with open(_one(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            k = short(r["Kernel_Name"])
+            if rx and not rx.fullmatch(k):
+                continue
+            agg[(k, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: (len(v), sum(v) / len(v)) for k, v in agg.items()}
+
+
+def _copy_kib(d, counter):
+    m = counter_means(d, r"__amd_rocclr_copyBuffer")
+    return m[("__amd_rocclr_copyBuffer", counter)][1]
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, kernel):
+    fk = counter_means(fetch_dir, re.escape(kernel))[(kernel, "FETCH_SIZE")]
+    wk = counter_means(write_dir, re.escape(kernel))[(kernel, "WRITE_SIZE")]
+    cf = _copy_kib(copy_fetch_dir, "FETCH_SIZE")
+    cw = _copy_kib(copy_write_dir, "WRITE_SIZE")
+    fetch_scale = copy_bytes / (cf * 1024.0)
+    write_scale = copy_bytes / (cw * 1024.0)
+    return {"kernel": kernel, "dispatches": fk[0], "fetch_kib": fk[1], "write_kib": wk[1],
+            "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+            "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+            "traffic_bytes": fk[1] * 1024.0 * fetch_scale + wk[1] * 1024.0 * write_scale}
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "stats":
+        rows = sorted(kernel_stats(argv[1]), key=lambda r: -r["total_us"])
+        print("| kernel | calls | total us | avg us | % |\n|---|---|---|---|---|")
+        for r in rows:
+            print(f"| {r['name']} | {r['calls']} | {r['total_us']:.1f} | {r['avg_us']:.1f} | "
+                  f"{r['percent']:.2f} |")
+    elif len(argv) >= 2 and argv[0] == "counters":
+        m = counter_means(argv[1], argv[2] if len(argv) > 2 else None)
+        print("| kernel | counter | dispatches | mean per dispatch |\n|---|---|---|---|")
+        for (k, c), (n, v) in sorted(m.items()):
+            print(f"| {k} | {c} | {n} | {v:.6g} |")
+    elif len(argv) == 7 and argv[0] == "traffic":
+        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6])))
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -188,7 +188,9 @@ def test_generated_kernels_compile_for_gfx950(lib):
     rng = np.random.default_rng(12)
     for c, opts in [(I.random_mixed(6, 40, rng, n_inputs=2, p_input=0.3), dict(tile_qubits=5, low_qubits=1)),
                     (I.rx_ry_rz_cz_ladder(11, 2), dict(tile_qubits=10, low_qubits=4)),
-                    (I.random_layers(9, 3, rng), dict(tile_qubits=8, low_qubits=3))]:
+                    (I.random_layers(9, 3, rng), dict(tile_qubits=8, low_qubits=3)),
+                    # 14-qubit tiles with the most gradient slots a pass may hold (LDS bound)
+                    (I.rx_ry_rz_cz_ladder(15, 6), dict(tile_qubits=14, low_qubits=6))]:
         p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, **opts)
         src = B.qsv_plan_codegen_source(p.handle)
         assert src.count("__global__") == p.info()["n_fwd_passes"] + p.info()["n_bwd_passes"]
