@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--fuse-width", type=int, default=None)
     ap.add_argument("--tile-qubits", type=int, default=None)
     ap.add_argument("--low-qubits", type=int, default=None)
+    ap.add_argument("--mfma", type=int, choices=(0, 1, 2), default=None,
+                    help="2x2 products on the matrix cores: 0 none, 1 forward kernels, 2 forward and backward")
+    ap.add_argument("--bwd-gate-by-gate", type=int, choices=(0, 1), default=None)
     ap.add_argument("--uneven-steps", type=int, default=15,
                     help="timed steps of the 512-circuit uneven set (0 = skip)")
     ap.add_argument("--quiet", action="store_true")
@@ -237,7 +240,8 @@ def main():
     circ, B, seed = inputs.workload(args.workload)
     W = circ.n_qubits
     opts = {k: v for k, v in (("fuse_width", args.fuse_width), ("tile_qubits", args.tile_qubits),
-                              ("low_qubits", args.low_qubits)) if v is not None}
+                              ("low_qubits", args.low_qubits), ("mfma", args.mfma),
+                              ("bwd_gate_by_gate", args.bwd_gate_by_gate)) if v is not None}
     t_plan = time.perf_counter()
     fused = binding.Plan(W, circ.gates, circ.n_weights, circ.n_inputs, method="fused", **opts)
     plan_ms = (time.perf_counter() - t_plan) * 1e3

@@ -113,7 +113,11 @@ typedef struct {
                             its gates' gradients are formed from the X, Y, Z
                             components taken after the chain, where that costs
                             fewer operations; 1: every gate is uncomputed on its own */
-    int32_t reserved;
+    int32_t mfma;        /* generated kernels: generic 2x2 products on the matrix
+                            cores (v_mfma_f32_4x4x1_16b: each lane multiplies its own
+                            amplitude pair, as a real 4-vector, by the gate's real 4x4
+                            form) in 1 (default): forward kernels, 2: forward and
+                            backward kernels; 0: everything on the vector ALU */
 } qsv_opts;
 
 typedef struct {
@@ -140,7 +144,8 @@ typedef struct {
 
 typedef struct qsv_plan_s qsv_plan_t;
 
-/* Fill *opts with the defaults (fused, k = 1, m = 12, c = 5, 256, codegen 1). */
+/* Fill *opts with the defaults (fused, k = 1, m = 12, c = 5, 256, codegen 1, chain
+ * products in the backward, mfma 1). */
 void qsv_default_opts(qsv_opts* opts);
 
 /*

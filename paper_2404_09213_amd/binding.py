@@ -44,7 +44,7 @@ class qsv_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("fuse_width", ctypes.c_int32),
                 ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
                 ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
-                ("bwd_gate_by_gate", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bwd_gate_by_gate", ctypes.c_int32), ("mfma", ctypes.c_int32)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -312,8 +312,10 @@ def qsv_last_error():
 # -- plan owner with torch-allocated workspaces -------------------------------------
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
-              max_pass_grads=None, codegen=None, bwd_gate_by_gate=None):
+              max_pass_grads=None, codegen=None, bwd_gate_by_gate=None, mfma=None):
     o = qsv_default_opts()
+    if mfma is not None:
+        o.mfma = int(mfma)
     if bwd_gate_by_gate is not None:
         o.bwd_gate_by_gate = int(bwd_gate_by_gate)
     if codegen is not None:

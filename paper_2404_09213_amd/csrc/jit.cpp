@@ -91,6 +91,7 @@ public:
     std::string prelude() const {
         return R"(
 typedef float2 f2;
+typedef float qsv_v4f __attribute__((ext_vector_type(4)));
 // float64 wavefront sum by DPP lane moves: pairs, quads, half rows, rows, then
 // row 0 -> 1, 2 -> 3 and rows 0-1 -> 2-3 broadcasts; lane 63 holds the total.
 template <int CTRL, int ROWMASK>
@@ -179,6 +180,14 @@ private:
 
     std::string act(const std::string& body) const { return guard_ ? "if (act) { " + body + " }" : body; }
 
+    // Matrix-core path for a generic 2x2: only where every lane of the wave
+    // executes it (matrix instructions run on all lanes regardless of the
+    // execution mask), i.e. not under a control outside the registers.
+    // opts.mfma: 1 forward kernels, 2 forward and backward kernels.
+    bool use_mfma(const DOp& op) const {
+        return p_->opts.mfma >= (bwd_ ? 2 : 1) && op.kind == OP_U2 && op.ctl < kCtlNonReg;
+    }
+
     int lq(int j) const { return ps_->lq[j]; }
 
     // global offset of register k (within the sample) in layout L
@@ -202,9 +211,14 @@ private:
     std::string lT_expr(const Layout& L) const { return scatter("t", L.nonreg); }
 
     void emit_exchange(const Layout& from, const Layout& to) {
-        o_ << "  {\n    const int l0_ = " << lT_expr(from) << ";\n"
+        // The empty asm statements make each exchange compute its LDS
+        // addresses afresh: otherwise the compiler keeps the addresses of
+        // every layout alive across the whole kernel (tens of registers).
+        o_ << "  {\n    int l0_ = " << lT_expr(from) << ";\n"
+           << "    __asm__ volatile(\"\" : \"+v\"(l0_));\n"
            << "    const int s0_ = l0_ ^ (((l0_ >> 5) ^ (l0_ >> 10)) & 31);\n"
-           << "    const int l1_ = " << lT_expr(to) << ";\n"
+           << "    int l1_ = " << lT_expr(to) << ";\n"
+           << "    __asm__ volatile(\"\" : \"+v\"(l1_));\n"
            << "    const int s1_ = l1_ ^ (((l1_ >> 5) ^ (l1_ >> 10)) & 31);\n";
         for (size_t ai = 0; ai < arrays_.size(); ++ai) {
             const std::string& A = arrays_[ai];
@@ -231,8 +245,21 @@ private:
         o_ << "    const float* M_ = " << mat_ptr(op.mat) << ";\n";
         switch (op.kind) {
         case OP_U2:
-            o_ << "    const float m0r = M_[0], m0i = M_[1], m1r = M_[2], m1i = M_[3], "
-                  "m2r = M_[4], m2i = M_[5], m3r = M_[6], m3i = M_[7];\n";
+            if (use_mfma(op)) {
+                // row (lane & 3) of the real 4x4 form of [[u00, u01], [u10, u11]] acting
+                // on (x.re, x.im, y.re, y.im): rows 0, 1 from u00, u01; rows 2, 3 from u10, u11
+                // entries read as wave-uniform values (scalar loads), then selected per lane
+                o_ << "    float u_[8];\n"
+                   << "    for (int i_ = 0; i_ < 8; ++i_) u_[i_] = __int_as_float(__builtin_amdgcn_readfirstlane("
+                      "__float_as_int(M_[i_])));\n"
+                   << "    const float ur_ = lo4_ ? u_[0] : u_[4], ui_ = lo4_ ? u_[1] : u_[5], "
+                      "vr_ = lo4_ ? u_[2] : u_[6], vi_ = lo4_ ? u_[3] : u_[7];\n"
+                   << "    const float a0_ = im4_ ? ui_ : ur_, a1_ = im4_ ? ur_ : -ui_, "
+                      "a2_ = im4_ ? vi_ : vr_, a3_ = im4_ ? vr_ : -vi_;\n";
+            } else {
+                o_ << "    const float m0r = M_[0], m0i = M_[1], m1r = M_[2], m1i = M_[3], "
+                      "m2r = M_[4], m2i = M_[5], m3r = M_[6], m3i = M_[7];\n";
+            }
             break;
         case OP_REAL:
             o_ << "    const float m0r = M_[0], m1r = M_[2], m2r = M_[4], m3r = M_[6];\n";
@@ -264,6 +291,17 @@ private:
             const int k1 = k | (1 << op.pos);
             const std::string x = rk(A, k), y = rk(A, k1);
             o_ << "      { const f2 x = " << x << ", y = " << y << ";\n";
+            if (op.kind == OP_U2 && use_mfma(op)) {
+                // 16 blocks of 4 lanes: lane 4b+j supplies row j of the matrix (A) and
+                // its own pair (B) and receives its pair's four outputs
+                o_ << "        qsv_v4f c_ = {0.f, 0.f, 0.f, 0.f};\n"
+                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a0_, x.x, c_, 0, 0, 0);\n"
+                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a1_, x.y, c_, 0, 0, 0);\n"
+                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a2_, y.x, c_, 0, 0, 0);\n"
+                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a3_, y.y, c_, 0, 0, 0);\n"
+                   << "        " << x << " = make_float2(c_[0], c_[1]); " << y << " = make_float2(c_[2], c_[3]); }\n";
+                continue;
+            }
             switch (op.kind) {
             case OP_U2:
                 o_ << "        " << x << " = make_float2(m0r * x.x - m0i * x.y + m1r * y.x - m1i * y.y, "
@@ -410,6 +448,7 @@ private:
         // per-row float32 partials of every gradient slot: [wave * 4 + row][slot]
         if (bwd_ && ng) o_ << "  __shared__ float red[" << nw * 4 * ng << "];\n";
         o_ << "  const int t = threadIdx.x;\n";
+        o_ << "  const int q4_ = t & 3; const bool lo4_ = q4_ < 2, im4_ = q4_ & 1; (void)lo4_; (void)im4_;\n";
         if (guard_) o_ << "  const bool act = t < " << T_ << ";\n";
         o_ << "  const unsigned tile = blockIdx.x;\n"
            << "  const int b = (int)(tile >> " << tb << ");\n"
@@ -487,7 +526,10 @@ private:
             // row reductions of this stage's gradient partials (float32 within a
             // 16-lane row); rows are combined in float64 at the end of the pass
             for (int j : stage_slots)
-                o_ << "  { const float r_ = qsv_row_sum(g" << j << "); if ((lane & 15) == 0) red[(wave * 4 + (lane >> 4)) * "
+                // every lane of a row holds the row's sum and stores it (same value,
+                // same address): no branch, which keeps the compiler's register
+                // allocation across the straight-line kernel intact
+                o_ << "  { const float r_ = qsv_row_sum(g" << j << "); red[(wave * 4 + (lane >> 4)) * "
                    << ng << " + " << j << "] = r_; }\n";
         }
         const bool write_back = !bwd_ || !(flags & PF_LAST_BWD);
@@ -538,7 +580,8 @@ std::string cache_path(const std::string& src, const std::string& arch) {
     const char* dir = std::getenv("QSV_JIT_CACHE");
     if (!dir || !*dir) return "";
     char b[40];
-    std::snprintf(b, sizeof b, "%016llx", (unsigned long long)fnv1a(src + "|" + arch));
+    // the tag changes whenever the compiler options below change
+    std::snprintf(b, sizeof b, "%016llx", (unsigned long long)fnv1a(src + "|" + arch + "|opts2"));
     return std::string(dir) + "/qsv_" + b + ".co";
 }
 
@@ -604,7 +647,7 @@ int compile_children(const std::string& clang, const std::vector<std::string>& s
                                              "--no-gpu-bundle-output", "-O3", "-std=c++17",
                                              "-include", "hip/hip_runtime.h",
                                              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                                             "-o", out, in};
+                                             "-mllvm", "-amdgpu-mfma-vgpr-form=1", "-o", out, in};
             std::vector<char*> argv;
             for (auto& a : args) argv.push_back(&a[0]);
             argv.push_back(nullptr);

@@ -18,12 +18,12 @@ pytestmark = pytest.mark.gpu
 
 # fused = generated per-plan kernels; fused_tables = table-driven kernels; per_gate = plain
 # method; fused_gbg = generated kernels with the backward uncomputing gate by gate (no
-# 1-qubit chain products)
+# 1-qubit chain products) and every 2x2 on the vector ALU (no matrix cores)
 METHODS = ["fused", "fused_tables", "per_gate", "fused_gbg"]
 _METHOD_OPTS = {"fused": {"method": "fused", "codegen": 1},
                 "fused_tables": {"method": "fused", "codegen": 0},
                 "per_gate": {"method": "per_gate"},
-                "fused_gbg": {"method": "fused", "codegen": 1, "bwd_gate_by_gate": 1}}
+                "fused_gbg": {"method": "fused", "codegen": 1, "bwd_gate_by_gate": 1, "mfma": 0}}
 
 
 def _opts(method, **extra):
