@@ -45,8 +45,8 @@ def parse():
     ap.add_argument("--fuse-width", type=int, default=None)
     ap.add_argument("--tile-qubits", type=int, default=None)
     ap.add_argument("--low-qubits", type=int, default=None)
-    ap.add_argument("--mfma", type=int, choices=(0, 1, 2), default=None,
-                    help="2x2 products on the matrix cores: 0 none, 1 forward kernels, 2 forward and backward")
+    ap.add_argument("--mfma", type=int, choices=range(8), default=None,
+                    help="2x2 products on the matrix cores, bits: 1 forward, 2 backward psi, 4 backward lambda")
     ap.add_argument("--bwd-gate-by-gate", type=int, choices=(0, 1), default=None)
     ap.add_argument("--uneven-steps", type=int, default=15,
                     help="timed steps of the 512-circuit uneven set (0 = skip)")

@@ -183,9 +183,13 @@ private:
     // Matrix-core path for a generic 2x2: only where every lane of the wave
     // executes it (matrix instructions run on all lanes regardless of the
     // execution mask), i.e. not under a control outside the registers.
-    // opts.mfma: 1 forward kernels, 2 forward and backward kernels.
+    // opts.mfma bits: 1 forward kernels, 2 backward psi array, 4 backward lambda array.
     bool use_mfma(const DOp& op) const {
-        return p_->opts.mfma >= (bwd_ ? 2 : 1) && op.kind == OP_U2 && op.ctl < kCtlNonReg;
+        return (p_->opts.mfma & (bwd_ ? 6 : 1)) && op.kind == OP_U2 && op.ctl < kCtlNonReg;
+    }
+    bool mfma_array(const std::string& A) const {
+        if (!bwd_) return p_->opts.mfma & 1;
+        return p_->opts.mfma & (A == "ps" ? 2 : 4);
     }
 
     int lq(int j) const { return ps_->lq[j]; }
@@ -256,6 +260,11 @@ private:
                       "vr_ = lo4_ ? u_[2] : u_[6], vi_ = lo4_ ? u_[3] : u_[7];\n"
                    << "    const float a0_ = im4_ ? ui_ : ur_, a1_ = im4_ ? ur_ : -ui_, "
                       "a2_ = im4_ ? vi_ : vr_, a3_ = im4_ ? vr_ : -vi_;\n";
+                bool valu_too = false;
+                for (const std::string& A : arrays_) valu_too |= !mfma_array(A);
+                if (valu_too)
+                    o_ << "    const float m0r = u_[0], m0i = u_[1], m1r = u_[2], m1i = u_[3], "
+                          "m2r = u_[4], m2i = u_[5], m3r = u_[6], m3i = u_[7];\n";
             } else {
                 o_ << "    const float m0r = M_[0], m0i = M_[1], m1r = M_[2], m1i = M_[3], "
                       "m2r = M_[4], m2i = M_[5], m3r = M_[6], m3i = M_[7];\n";
@@ -286,22 +295,38 @@ private:
         return v;
     }
 
+    // Matrix-core form of a generic 2x2 over every pair of every state array:
+    // 16 blocks of 4 lanes; lane 4b+j supplies row j of the gate's real 4x4
+    // form (A operand) and its own pair (B operand) and receives its pair's
+    // four outputs. The four rank-1 steps are issued step by step across all
+    // pairs, so consecutive matrix instructions are independent.
+    void emit_pairs_mfma(const DOp& op) {
+        std::vector<std::pair<std::string, std::string>> xy;
+        for (const std::string& A : arrays_)
+            if (mfma_array(A))
+                for (int k : pairs(op.pos, op.ctl)) xy.emplace_back(rk(A, k), rk(A, k | (1 << op.pos)));
+        const int n = (int)xy.size();
+        o_ << "    {\n";
+        for (int i = 0; i < n; ++i)
+            o_ << "      qsv_v4f c" << i << "_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a0_, " << xy[i].first
+               << ".x, qsv_v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);\n";
+        for (int st = 1; st < 4; ++st)
+            for (int i = 0; i < n; ++i) {
+                const std::string src = st == 1 ? xy[i].first + ".y" : st == 2 ? xy[i].second + ".x" : xy[i].second + ".y";
+                o_ << "      c" << i << "_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a" << st << "_, " << src << ", c" << i
+                   << "_, 0, 0, 0);\n";
+            }
+        for (int i = 0; i < n; ++i)
+            o_ << "      " << xy[i].first << " = make_float2(c" << i << "_[0], c" << i << "_[1]); " << xy[i].second
+               << " = make_float2(c" << i << "_[2], c" << i << "_[3]);\n";
+        o_ << "    }\n";
+    }
+
     void emit_pair_op(const DOp& op, const std::string& A) {
         for (int k : pairs(op.pos, op.ctl)) {
             const int k1 = k | (1 << op.pos);
             const std::string x = rk(A, k), y = rk(A, k1);
             o_ << "      { const f2 x = " << x << ", y = " << y << ";\n";
-            if (op.kind == OP_U2 && use_mfma(op)) {
-                // 16 blocks of 4 lanes: lane 4b+j supplies row j of the matrix (A) and
-                // its own pair (B) and receives its pair's four outputs
-                o_ << "        qsv_v4f c_ = {0.f, 0.f, 0.f, 0.f};\n"
-                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a0_, x.x, c_, 0, 0, 0);\n"
-                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a1_, x.y, c_, 0, 0, 0);\n"
-                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a2_, y.x, c_, 0, 0, 0);\n"
-                   << "        c_ = __builtin_amdgcn_mfma_f32_4x4x1f32(a3_, y.y, c_, 0, 0, 0);\n"
-                   << "        " << x << " = make_float2(c_[0], c_[1]); " << y << " = make_float2(c_[2], c_[3]); }\n";
-                continue;
-            }
             switch (op.kind) {
             case OP_U2:
                 o_ << "        " << x << " = make_float2(m0r * x.x - m0i * x.y + m1r * y.x - m1i * y.y, "
@@ -375,7 +400,9 @@ private:
         }
         const bool nonreg_ctl = op.ctl >= kCtlNonReg;
         if (nonreg_ctl) o_ << "    if ((gT >> " << (op.ctl & 0xFF) << ") & 1) {\n";
-        for (const std::string& A : arrays_) emit_pair_op(op, A);
+        if (use_mfma(op)) emit_pairs_mfma(op);
+        for (const std::string& A : arrays_)
+            if (!use_mfma(op) || !mfma_array(A)) emit_pair_op(op, A);
         if (nonreg_ctl) o_ << "    }\n";
         o_ << "  }\n";
     }
@@ -513,24 +540,21 @@ private:
                 emit_exchange(cur, L);
                 cur = L;
             }
-            std::vector<int> stage_slots;
             for (int oi = st.op0; oi < st.op1; ++oi) {
                 const DOp& op = p_->ops[oi];
                 if (op.kind >= OP_GX) {
                     emit_grad(op);
-                    stage_slots.push_back(op.slot);
+                    // row reduction of the partial right away (float32 within a
+                    // 16-lane row; rows are combined in float64 at the end of the
+                    // pass). Every lane of a row holds the row's sum and stores it
+                    // (same value, same address): no branch, which keeps the
+                    // compiler's register allocation across the kernel intact.
+                    o_ << "  { const float r_ = qsv_row_sum(g" << op.slot << "); red[(wave * 4 + (lane >> 4)) * "
+                       << ng << " + " << op.slot << "] = r_; }\n";
                 } else {
                     emit_apply(op);
                 }
             }
-            // row reductions of this stage's gradient partials (float32 within a
-            // 16-lane row); rows are combined in float64 at the end of the pass
-            for (int j : stage_slots)
-                // every lane of a row holds the row's sum and stores it (same value,
-                // same address): no branch, which keeps the compiler's register
-                // allocation across the straight-line kernel intact
-                o_ << "  { const float r_ = qsv_row_sum(g" << j << "); red[(wave * 4 + (lane >> 4)) * "
-                   << ng << " + " << j << "] = r_; }\n";
         }
         const bool write_back = !bwd_ || !(flags & PF_LAST_BWD);
         if (write_back) {

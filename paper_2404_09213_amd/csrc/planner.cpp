@@ -381,6 +381,11 @@ std::vector<std::pair<uint32_t, std::vector<int>>> group_stages(const std::vecto
 struct PassBuilder {
     qsv_plan_t* p;
     bool backward;
+    // backward: first gate (program order) on each qubit. A unit holding the
+    // first gate on every qubit it touches needs no uncompute: nothing later
+    // in the backward touches those qubits, and Im<l|P|psi> for P on other
+    // qubits does not change under a unitary applied to both states on them.
+    std::vector<int> first_on;
 
     void build(const std::vector<int>& gates, uint32_t dense, int m, int c, int flags,
                std::vector<DPass>& out, std::vector<int32_t>& order) {
@@ -431,6 +436,14 @@ struct PassBuilder {
                 else order.insert(order.end(), U.gates.begin(), U.gates.end());
                 const qsv_gate& G = p->gates[U.gates[0]];
                 const bool is_cz = U.gates.size() == 1 && G.kind == QSV_CZ;
+                auto starts_timelines = [&]() {
+                    if (!backward || first_on.empty()) return false;
+                    const qsv_gate& G0 = p->gates[U.gates[0]];
+                    for (int b = 0; b < W; ++b)
+                        if ((qmask(G0) >> b & 1) && first_on[b] != U.gates[0]) return false;
+                    return true;
+                };
+                if (is_cz && starts_timelines()) continue;
                 if (is_cz) {
                     if (sign_op < 0) {
                         DOp o;
@@ -535,6 +548,7 @@ struct PassBuilder {
                         p->gouts.push_back(go);
                     }
                 }
+                if (starts_timelines()) continue;
                 DOp o;
                 std::memset(&o, 0, sizeof o);
                 o.kind = recipe_class(p, U.gates);
@@ -723,14 +737,19 @@ int build_plan(qsv_plan_t* p) {
     {
         std::vector<uint32_t> dense;
         auto passes = pack_passes(p, split(p, body, o.fuse_width), m, c, 1 << 30, dense);
-        PassBuilder pb{p, false};
+        PassBuilder pb{p, false, {}};
         for (size_t i = 0; i < passes.size(); ++i)
             pb.build(passes[i], dense[i], m, c, 0, p->fwd_pass, p->fwd_order);
     }
     {
         std::vector<uint32_t> dense;
         auto passes = pack_passes(p, p->blocks, m, c, max_grads, dense);
-        PassBuilder pb{p, true};
+        PassBuilder pb{p, true, std::vector<int>(W, p->n_gates)};
+        for (int g = p->n_gates - 1; g >= 0; --g) {
+            const qsv_gate& G = p->gates[g];
+            pb.first_on[G.q0] = g;
+            if (is_two(G.kind)) pb.first_on[G.q1] = g;
+        }
         const int n = (int)passes.size();
         for (int i = n - 1; i >= 0; --i) {
             int flags = 0;

@@ -1486,7 +1486,7 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
     if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
-    if (o.mfma < 0 || o.mfma > 2) { set_error("mfma must be 0, 1 or 2"); return QSV_ERR_ARG; }
+    if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
@@ -1866,7 +1866,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.low_qubits < 0 || o.low_qubits >= o.tile_qubits) { set_error("low_qubits must be in 0..tile_qubits-1"); return QSV_ERR_ARG; }
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
     if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
-    if (o.mfma < 0 || o.mfma > 2) { set_error("mfma must be 0, 1 or 2"); return QSV_ERR_ARG; }
+    if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     std::vector<CircuitIn> cs;
     int64_t row = 0;
     for (int c = 0; c < n_circuits; ++c) {
