@@ -118,6 +118,11 @@ typedef struct {
                             amplitude pair, as a real 4-vector, by the gate's real 4x4
                             form) in 1 (default): forward kernels, 2: forward and
                             backward kernels; 0: everything on the vector ALU */
+    int32_t weight_remap; /* 1: every weight angle w enters its gate as pi tanh(w)
+                            (quantum weight remapping, section "Additional
+                            Optimizations": weights mapped into (-pi, pi) by tanh);
+                            weight gradients are then with respect to w. 0 (default): off */
+    int32_t reserved[3];
 } qsv_opts;
 
 typedef struct {

@@ -156,6 +156,22 @@ def gate_matrix(kind, theta=0.0):
     return out.reshape(2, 2)
 
 
+def remap(weights):
+    """Quantum weight remapping (section "Additional Optimizations"): weights
+    are mapped into (-pi, pi) by a smooth function; the paper names tanh and
+    the range [-pi, pi], read here as w -> pi tanh(w)."""
+    return math.pi * np.tanh(np.asarray(weights, dtype=np.float64))
+
+
+def adjoint_remapped(n_qubits, gates, weights, inputs, batch, grad_out, want_state=False):
+    """`adjoint` of the circuit whose gates take pi tanh(w) for every weight w;
+    weight gradients with respect to w (chain rule: pi (1 - tanh(w)^2))."""
+    w = np.asarray(weights, dtype=np.float64).reshape(-1)
+    out = adjoint(n_qubits, gates, remap(w), inputs, batch, grad_out, want_state)
+    gw = out[0] * (math.pi * (1.0 - np.tanh(w) ** 2))
+    return (gw,) + tuple(out[1:])
+
+
 def loss(n_qubits, gates, weights, inputs, batch, grad_out, shift=None):
     """Per-sample L_b = sum_i g[b,i] <Z_i>_b (float64, shape (batch,))."""
     E = expval(n_qubits, forward(n_qubits, gates, weights, inputs, batch, shift))

@@ -44,7 +44,8 @@ class qsv_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("fuse_width", ctypes.c_int32),
                 ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
                 ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
-                ("bwd_gate_by_gate", ctypes.c_int32), ("mfma", ctypes.c_int32)]
+                ("bwd_gate_by_gate", ctypes.c_int32), ("mfma", ctypes.c_int32),
+                ("weight_remap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -312,8 +313,11 @@ def qsv_last_error():
 # -- plan owner with torch-allocated workspaces -------------------------------------
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
-              max_pass_grads=None, codegen=None, bwd_gate_by_gate=None, mfma=None):
+              max_pass_grads=None, codegen=None, bwd_gate_by_gate=None, mfma=None,
+              weight_remap=None):
     o = qsv_default_opts()
+    if weight_remap is not None:
+        o.weight_remap = int(weight_remap)
     if mfma is not None:
         o.mfma = int(mfma)
     if bwd_gate_by_gate is not None:

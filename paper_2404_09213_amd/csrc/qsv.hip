@@ -74,6 +74,20 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// float32 sum over the 16 lanes of a DPP row (pairs, quads, half rows, rows);
+// every lane of the row ends with the row's total. Fixed order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float row_sum(float v) {
+    v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);  // row_half_mirror
+    v += dpp_f<0x140>(v);  // row_mirror
+    return v;
+}
+
 __device__ __forceinline__ float im_conj_mul(float2 l, float2 p) { return l.x * p.y - l.y * p.x; }
 __device__ __forceinline__ float re_conj_mul(float2 l, float2 p) { return l.x * p.x + l.y * p.y; }
 
@@ -91,7 +105,7 @@ __device__ __forceinline__ int64_t insert_bit(int64_t x, int s, int v) {
 __global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restrict__ recipes,
                        const int32_t* __restrict__ rg, int n_recipes,
                        const float* __restrict__ weights, const float* __restrict__ inputs,
-                       int n_inputs, int n_shared, int n_ps, float* __restrict__ mats) {
+                       int n_inputs, int n_shared, int n_ps, int remap, float* __restrict__ mats) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (r >= n_recipes) return;
@@ -101,7 +115,10 @@ __global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restric
     for (int i = 0; i < R.count; ++i) {
         const DGate& G = gates[rg[R.first + i]];
         double th = 0.0;
-        if (G.src == QSV_SRC_WEIGHT) th = (double)weights[G.idx];
+        if (G.src == QSV_SRC_WEIGHT) {
+            th = (double)weights[G.idx];
+            if (remap) th = M_PI * tanh(th);  // weight remapping into (-pi, pi)
+        }
         else if (G.src == QSV_SRC_INPUT) th = (double)inputs[(size_t)b * n_inputs + G.idx];
         double s, c;
         sincos(0.5 * th, &s, &c);
@@ -240,7 +257,8 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
                                                      const int64_t* __restrict__ pu,
                                                      const int32_t* __restrict__ nchv,
                                                      double* __restrict__ gw,
-                                                     double* __restrict__ gx) {
+                                                     double* __restrict__ gx,
+                                                     const float* __restrict__ weights, int remap) {
     __shared__ double red[256];
     const int t = threadIdx.x;
     const int o = blockIdx.x;  // output index: weights first, then (b, input)
@@ -278,7 +296,14 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
         __syncthreads();
     }
     if (t == 0) {
-        if (o < n_weights) gw[j] = red[0];
+        if (o < n_weights) {
+            double f = 1.0;
+            if (remap) {  // d(pi tanh w)/dw
+                const double th = tanh((double)weights[j]);
+                f = M_PI * (1.0 - th * th);
+            }
+            gw[j] = red[0] * f;
+        }
         else if (gx) gx[(size_t)b0 * n_inputs + j] = red[0];
     }
 }
@@ -847,7 +872,11 @@ __device__ __forceinline__ void pass_bwd_tile(
     const int nthr = 1 << (m - kRegBits);
     const bool act = t < nthr;
     const int nwaves = (int)(blockDim.x >> 6);
-    double* red = reinterpret_cast<double*>(lds + (1 << m));
+    // float32 partials per 16-lane row and component slot, then float64 sums
+    const int ng = P->n_gslots;
+    const int nrows = nwaves * 4;
+    float* red = reinterpret_cast<float*>(lds + (1 << m));
+    double* csum = reinterpret_cast<double*>(lds + (1 << m) + ((nrows * ng + 1) >> 1));
     const int tbits = W - m;
     const int base = tile_base_of(P, tbits, tis);
     const int flags = P->flags;
@@ -901,8 +930,8 @@ __device__ __forceinline__ void pass_bwd_tile(
         for (int oi = stg.op0; oi < stg.op1; ++oi) {
             const DOp op = O[oi];
             if (op.kind >= OP_GX) {
-                const double r = wave_sum((double)grad_op(op, ps, lm, L.gT));
-                if (lane == 0) red[wave * P->n_gslots + op.slot] = r;
+                // every lane of a row stores the row's sum (same value, same address)
+                red[(wave * 4 + (lane >> 4)) * ng + op.slot] = row_sum(grad_op(op, ps, lm, L.gT));
             } else {
                 M2 M{};
                 if (op.kind != OP_SIGN && op.kind != OP_SWAP) M = load_m2(mat_ptr(mats, op.mat, b, n_shared, n_ps));
@@ -931,23 +960,21 @@ __device__ __forceinline__ void pass_bwd_tile(
         }
     }
     __syncthreads();
-    const int ng = P->n_gslots;
     const int64_t nch = int64_t(1) << tbits;
-    // component sums (wave 0's entry of slot j is only touched by thread j)
     for (int j = t; j < ng; j += blockDim.x) {
         double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += red[w * ng + j];
-        red[j] = s;
+        for (int r = 0; r < nrows; ++r) s += (double)red[r * ng + j];
+        csum[j] = s;
     }
     __syncthreads();
     for (int j = t; j < P->n_gout; j += blockDim.x) {
         const DGOut o = gouts[P->gout0 + j];
         double v;
         if (o.axis < 0) {
-            v = red[o.c0];
+            v = csum[o.c0];
         } else {
-            const double cx = o.c0 >= 0 ? red[o.c0] : 0.0, cy = o.c1 >= 0 ? red[o.c1] : 0.0,
-                         cz = o.c2 >= 0 ? red[o.c2] : 0.0;
+            const double cx = o.c0 >= 0 ? csum[o.c0] : 0.0, cy = o.c1 >= 0 ? csum[o.c1] : 0.0,
+                         cz = o.c2 >= 0 ? csum[o.c2] : 0.0;
             v = chain_grad(mat_ptr(mats, o.mat, b, n_shared, n_ps), o.axis, cx, cy, cz);
         }
         part[B * pu[o.ord] + (int64_t)b * nch + tis] = v;
@@ -1328,7 +1355,7 @@ int run_coef(const qsv_plan_t* p, DeviceTables* T, const float* w, const float* 
     dim3 grid((nr + 127) / 128, (unsigned)(p->n_ps_mats ? B : 1));
     hipEvent_t ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_coef, grid, dim3(128), 0, s, T->gates, T->recipes, T->recipe_gates, nr,
-                       w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, mats);
+                       w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, (int)p->opts.weight_remap, mats);
     prof_end(p, s, ev, K_COEF, 32.0 * ((double)p->n_shared_mats + (double)B * p->n_ps_mats), 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
@@ -1410,10 +1437,18 @@ int get_queue(const qsv_plan_t* p, DeviceTables* T, int64_t B, DeviceTables::Que
     return QSV_OK;
 }
 
+// Backward LDS: the tile (8 B per amplitude), float32 row partials
+// [rows][slots], then float64 component sums (8-byte aligned).
+size_t bwd_lds(int m, int threads, int maxg) {
+    const size_t rows = (size_t)(threads / 64) * 4;
+    const size_t part = ((rows * maxg + 1) / 2) * 8;
+    return (size_t(1) << m) * 8 + part + (size_t)maxg * 8;
+}
+
 size_t multi_lds(const qsv_plan_t* p) {
     int maxg = 0;
     for (auto& ps : p->bwd_pass) maxg = std::max(maxg, (int)ps.n_gslots);
-    return (size_t(1) << kMaxTileQubitsTables) * 8 + 4 * (size_t)maxg * 8;
+    return bwd_lds(kMaxTileQubitsTables, 256, maxg);
 }
 
 
@@ -1428,7 +1463,7 @@ size_t pass_lds_bwd(const qsv_plan_t* p) {
     const int threads = std::max(64, 1 << (m - kRegBits));
     int maxg = 0;
     for (auto& ps : p->bwd_pass) maxg = std::max(maxg, (int)ps.n_gslots);
-    return (size_t(1) << m) * 8 + (size_t)(threads / 64) * maxg * 8;
+    return bwd_lds(m, threads, maxg);
 }
 
 }  // namespace
@@ -1487,6 +1522,7 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
     if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
+    if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
@@ -1844,7 +1880,8 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
         hipEvent_t ev = prof_begin(p, s);
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)n_out), dim3(256), 0, s,
                            (const double*)part, T->grad_csr, p->n_weights, p->n_inputs, (int)B,
-                           (const int64_t*)T->pu, (const int32_t*)T->nchv, gw, gx);
+                           (const int64_t*)T->pu, (const int32_t*)T->nchv, gw, gx, w,
+                           (int)p->opts.weight_remap);
         prof_end(p, s, ev, K_GRAD_REDUCE, 8.0 * (double)std::max<int64_t>(p->pu_total, 1) * B, 0.0);
     }
     HIP_TRY(hipGetLastError());
@@ -1867,6 +1904,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.max_pass_grads < 1 || o.max_pass_grads > 256) { set_error("max_pass_grads must be in 1..256"); return QSV_ERR_ARG; }
     if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
+    if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
     std::vector<CircuitIn> cs;
     int64_t row = 0;
     for (int c = 0; c < n_circuits; ++c) {

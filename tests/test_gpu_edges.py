@@ -1,0 +1,143 @@
+"""Edge cases of the GPU path: empty circuits, circuits without parameters or
+without inputs, the largest batch, and the largest qubit count (30 qubits,
+checked by closed forms that hold at any size).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2404_09213_amd import inputs as I
+
+from .helpers import AMP_TOL, EXP_TOL, grad_close, gpu_run, oracle_run
+
+METHODS = {"fused": {"method": "fused"}, "fused_tables": {"method": "fused", "codegen": 0},
+           "per_gate": {"method": "per_gate"}}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", list(METHODS))
+@pytest.mark.parametrize("W", [1, 3, 5, 13])
+def test_empty_circuit_is_ground_state(method, W):
+    print(f"[edges] empty W={W} {method}", flush=True)
+    c = I.Circuit(W, name=f"empty{W}")
+    B = 3
+    got = gpu_run(c, np.zeros(0, np.float32), np.zeros((B, 0), np.float32), B, g=np.ones((B, W)),
+                  **METHODS[method])
+    st = got["state"].cpu().numpy()
+    want = np.zeros_like(st)
+    want[:, 0] = 1.0
+    assert np.array_equal(st, want)
+    assert np.array_equal(got["E"].cpu().numpy(), np.ones((B, W)))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", list(METHODS))
+def test_fixed_gates_only_and_inputs_only(orc, method):
+    rng = np.random.default_rng(41)
+    print(f"[edges] fixed-only / inputs-only {method}", flush=True)
+    c = I.random_mixed(9, 80, rng, n_inputs=0, p_input=0.0)
+    fixed = I.Circuit(9, name="fixed_only")
+    for (k, q0, q1, src, idx) in c.gates:
+        if src == "none":
+            fixed.gates.append((k, q0, q1, src, idx))
+    B = 4
+    g = I.draw_grad_out(fixed, B, 5)
+    x0 = np.zeros((B, 0), np.float32)
+    got = gpu_run(fixed, np.zeros(0, np.float32), x0, B, g, **METHODS[method])
+    ref = oracle_run(orc, fixed, np.zeros(0), x0, B, g)
+    assert np.abs(got["state"].cpu().numpy() - ref["state"]).max() <= AMP_TOL
+    assert np.abs(got["E"].cpu().numpy() - ref["E"]).max() <= EXP_TOL
+
+    # every angle from the inputs (no weights)
+    c2 = I.random_mixed(8, 90, rng, n_inputs=5, p_input=1.0)
+    assert c2.n_weights == 0 and c2.n_inputs == 5
+    w, x = I.draw_angles(c2, B, 9)
+    g2 = I.draw_grad_out(c2, B, 9)
+    got = gpu_run(c2, w, x, B, g2, **METHODS[method])
+    ref = oracle_run(orc, c2, w, x, B, g2)
+    assert np.abs(got["state"].cpu().numpy() - ref["state"]).max() <= AMP_TOL
+    ok, rel = grad_close(got["gx"].cpu().numpy(), ref["gx"])
+    assert ok, rel
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", list(METHODS))
+def test_largest_batch(orc, method):
+    """65535 samples (the batch limit) of a 4-qubit circuit with inputs."""
+    print(f"[edges] B=65535 {method}", flush=True)
+    c = I.rx_ry_rz_cz_ladder(4, 2)
+    B = 65535
+    w, x = I.draw_angles(c, B, 77)
+    g = I.draw_grad_out(c, B, 77)
+    got = gpu_run(c, w, x, B, g, **METHODS[method])
+    ref = oracle_run(orc, c, w, x, B, g)
+    assert np.abs(got["state"].cpu().numpy() - ref["state"]).max() <= AMP_TOL
+    assert np.abs(got["E"].cpu().numpy() - ref["E"]).max() <= EXP_TOL
+    ok, rel = grad_close(got["gw"].cpu().numpy(), ref["gw"])
+    assert ok, ("weights", rel)
+    ok, rel = grad_close(got["gx"].cpu().numpy(), ref["gx"])
+    assert ok, ("inputs", rel)
+
+
+def _cascade_circuit(W):
+    """RY(theta_q) on every qubit, then CNOT(q, q+1) for q = 0..W-2 in order."""
+    c = I.Circuit(W, name=f"cascade{W}")
+    for q in range(W):
+        c.weight("RY", q)
+    for q in range(W - 1):
+        c.fixed("CNOT", q, q + 1)
+    return c
+
+
+def _cascade_closed_form(W, theta, idx):
+    th = np.asarray(theta, dtype=np.float64)
+    E = np.cumprod(np.cos(th))
+    dE = -np.tan(th) * np.cumsum(E[::-1])[::-1]
+    amps = []
+    for x in idx:
+        bits = [(x >> (W - 1 - q)) & 1 for q in range(W)]  # qubit q = bit W-1-q
+        pre = [bits[0]] + [bits[q] ^ bits[q - 1] for q in range(1, W)]
+        a = 1.0
+        for q in range(W):
+            a *= math.sin(th[q] / 2) if pre[q] else math.cos(th[q] / 2)
+        amps.append(a)
+    return E, dE, np.array(amps)
+
+
+def test_cascade_closed_form_matches_oracle(orc):
+    """The closed forms used at 30 qubits, checked against the oracle at 10."""
+    W = 10
+    c = _cascade_circuit(W)
+    theta = np.random.default_rng(3).uniform(0.05, 0.35, W)
+    gw, gx, st = orc.adjoint(W, c.gates, theta, np.zeros((1, 0)), 1, np.ones((1, W)), want_state=True)
+    idx = list(range(1 << W))
+    E, dE, amps = _cascade_closed_form(W, theta, idx)
+    assert np.abs(orc.expval(W, st)[0] - E).max() < 1e-12
+    assert np.abs(gw - dE).max() < 1e-12
+    assert np.abs(st[0] - amps).max() < 1e-12
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", ["fused", "per_gate"])
+def test_30_qubits_closed_form(method):
+    """30 qubits (the limit), batch 1, 8 GiB state. The CNOT cascade maps Z_j to
+    Z_0 ... Z_j, so <Z_j> = prod_{q <= j} cos(theta_q); amplitude x equals the
+    product state's amplitude at x'_j = x_j xor x_{j-1}; with L = sum_j <Z_j>,
+    dL/dtheta_q = -tan(theta_q) sum_{j >= q} <Z_j>."""
+    import torch
+    W = 30
+    print(f"[edges] W=30 cascade {method}", flush=True)
+    c = _cascade_circuit(W)
+    rng = np.random.default_rng(30)
+    theta = rng.uniform(0.05, 0.35, W).astype(np.float32)
+    got = gpu_run(c, theta, np.zeros((1, 0), np.float32), 1, np.ones((1, W)), **METHODS[method])
+    idx = [0, 1, 2, 5, 12345, (1 << 29) + 777, (1 << 30) - 1, 0x2AAAAAAA]
+    E, dE, amps = _cascade_closed_form(W, theta, idx)
+    assert np.abs(got["E"].cpu().numpy()[0] - E).max() <= EXP_TOL
+    ok, rel = grad_close(got["gw"].cpu().numpy(), dE)
+    assert ok, rel
+    st = got["state"][0].index_select(0, torch.tensor(idx, device=got["state"].device)).cpu().numpy()
+    assert np.abs(st - amps).max() <= AMP_TOL
+    del got
+    torch.cuda.empty_cache()

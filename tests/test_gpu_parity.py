@@ -192,3 +192,25 @@ def test_generated_equals_table_driven_state():
     a = gpu_run(c, w, x, 3, **_opts("fused"))
     b = gpu_run(c, w, x, 3, **_opts("fused_tables"))
     assert np.abs(a["state"].cpu().numpy() - b["state"].cpu().numpy()).max() < 2e-6
+
+
+@pytest.mark.parametrize("method", ["fused", "fused_tables", "per_gate"])
+def test_weight_remap(orc, method):
+    """Weights enter as pi tanh(w) (section "Additional Optimizations");
+    gradients with respect to the raw weights."""
+    rng = np.random.default_rng(91)
+    c = I.random_mixed(9, 120, rng, n_inputs=3, p_input=0.2)
+    B = 3
+    w, x = I.draw_angles(c, B, 91)
+    w = (w - np.float32(math.pi)) * np.float32(0.8)  # raw weights over [-2.5, 2.5]
+    g = I.draw_grad_out(c, B, 91)
+    print(f"[parity] weight remap {method}", flush=True)
+    got = gpu_run(c, w, x, B, g, **_opts(method, weight_remap=1))
+    gw, gx, st = orc.adjoint_remapped(c.n_qubits, c.gates, w.astype(np.float64),
+                                      x.astype(np.float64), B, g, want_state=True)
+    assert np.abs(got["state"].cpu().numpy() - st).max() <= AMP_TOL
+    assert np.abs(got["E"].cpu().numpy() - orc.expval(c.n_qubits, st)).max() <= EXP_TOL
+    ok, rel = grad_close(got["gw"].cpu().numpy(), gw)
+    assert ok, ("weights", rel)
+    ok, rel = grad_close(got["gx"].cpu().numpy(), gx)
+    assert ok, ("inputs", rel)

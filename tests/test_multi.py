@@ -78,11 +78,12 @@ def test_uneven_set_shape():
 
 # -- GPU parity ---------------------------------------------------------------------------
 
-def _run_multi(cs, batch, seed, orc, check_ids=None):
+def _run_multi(cs, batch, seed, orc, check_ids=None, **opts):
     import torch
     dev = torch.device("cuda:0")
     w, x, ws, xs = _draw(cs, batch, seed)
-    mp = B.MultiPlan(cs)
+    mp = B.MultiPlan(cs, **opts)
+    adjoint = orc.adjoint_remapped if opts.get("weight_remap") else orc.adjoint
     g = np.random.default_rng(seed).uniform(-1, 1, size=(batch, mp.n_out))
     wt = torch.from_numpy(w).to(dev)
     xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
@@ -103,7 +104,7 @@ def _run_multi(cs, batch, seed, orc, check_ids=None):
         n = c.n_qubits
         print(f"[multi] circuit {i}: W={n} gates={len(c.gates)}", flush=True)
         gi = g[:, off["qubit"]:off["qubit"] + n]
-        rw, rx, rs = orc.adjoint(n, c.gates, ws[i].astype(np.float64), xs[i].astype(np.float64), batch,
+        rw, rx, rs = adjoint(n, c.gates, ws[i].astype(np.float64), xs[i].astype(np.float64), batch,
                                  gi, want_state=True)
         got_st = st[:, off["amp"]:off["amp"] + (1 << n)]
         assert np.abs(got_st - rs).max() <= AMP_TOL, i
@@ -118,6 +119,11 @@ def _run_multi(cs, batch, seed, orc, check_ids=None):
 @pytest.mark.gpu
 def test_multi_small_mixed(orc):
     _run_multi(_mixed_set(11, 9, 4, 13), 2, 11, orc)
+
+
+@pytest.mark.gpu
+def test_multi_weight_remap(orc):
+    _run_multi(_mixed_set(12, 5, 4, 11), 2, 12, orc, weight_remap=1)
 
 
 @pytest.mark.gpu

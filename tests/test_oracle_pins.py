@@ -360,3 +360,38 @@ def test_adjoint_vs_shift_sampled_w12(orc):
         assert abs(gw[j] - sw[j]) < 1e-10
         assert abs(gw[j] - fw[j]) < 1e-6
     assert np.max(np.abs(gx[:, 3] - sx[3])) < 1e-10
+
+
+# -- weight remapping (section "Additional Optimizations") ----------------------
+
+def test_remap_range_and_values(orc):
+    w = np.array([0.0, math.atanh(0.5), -math.atanh(0.5), 30.0, -30.0])
+    r = orc.remap(w)
+    assert r[0] == 0.0
+    assert abs(r[1] - math.pi / 2) < 1e-15 and abs(r[2] + math.pi / 2) < 1e-15
+    assert abs(r[3] - math.pi) < 1e-12 and abs(r[4] + math.pi) < 1e-12
+    x = np.linspace(-5, 5, 101)
+    assert np.all(np.abs(orc.remap(x)) < math.pi) and np.all(np.diff(orc.remap(x)) > 0)
+
+
+def test_remapped_adjoint_vs_fd(orc):
+    """Gradients with respect to the raw weights through pi tanh(w), against
+    central differences of the loss taken through the remap."""
+    W, B = 5, 2
+    rng = np.random.default_rng(61)
+    c = I.random_mixed(W, 30, rng, n_inputs=2, p_input=0.25)
+    w, x = I.draw_angles(c, B, 61)
+    w64, x64 = w.astype(np.float64), x.astype(np.float64)
+    g = I.draw_grad_out(c, B, 61)
+    gw, gx = orc.adjoint_remapped(W, c.gates, w64, x64, B, g)
+    h = 1e-4
+    for j in range(c.n_weights):
+        wp, wm = w64.copy(), w64.copy()
+        wp[j] += h
+        wm[j] -= h
+        fd = (orc.loss(W, c.gates, orc.remap(wp), x64, B, g).sum()
+              - orc.loss(W, c.gates, orc.remap(wm), x64, B, g).sum()) / (2 * h)
+        assert abs(gw[j] - fd) < 1e-6, (j, gw[j], fd)
+    # input gradients are unchanged by the remap (it acts on weights only)
+    gw0, gx0 = orc.adjoint(W, c.gates, orc.remap(w64), x64, B, g)
+    assert np.array_equal(gx, gx0)
