@@ -11,9 +11,10 @@ computed as psi^dagger (I (x) ... (x) Z (x) ... (x) I) psi, with no bit
 arithmetic anywhere. Matrices are written here from their definitions,
 independently of the C oracle.
 
-Multi-qubit gates are expanded through projectors on the control:
-CU(c, t) = |0><0|_c (x) I + |1><1|_c (x) U_t, each term a Kronecker product
-of one 2x2 factor per qubit, qubit 0 leftmost.
+Multi-qubit gates are expanded through projectors on the controls:
+CU(c, t) = |0><0|_c (x) I + |1><1|_c (x) U_t, and with two controls the sum
+over the four control patterns, U_t only on |11>; each term a Kronecker
+product of one 2x2 factor per qubit, qubit 0 leftmost.
 """
 from __future__ import annotations
 
@@ -49,16 +50,26 @@ def expand_1q(W, w, R):
 
 
 def expand_controlled(W, c, t, U):
-    f0 = [I2] * W
-    f0[c] = P0
-    f1 = [I2] * W
-    f1[c] = P1
-    f1[t] = U
-    return kron_all(f0) + kron_all(f1)
+    return expand_multi_controlled(W, [c], t, U)
+
+
+def expand_multi_controlled(W, controls, t, U):
+    """sum over control patterns p of (x)_c |p_c><p_c| (x) (U_t if all ones else I):
+    every term a Kronecker product of one 2x2 factor per qubit."""
+    out = np.zeros((1 << W, 1 << W), dtype=np.complex128)
+    for pattern in range(1 << len(controls)):
+        f = [I2] * W
+        for j, c in enumerate(controls):
+            f[c] = P1 if (pattern >> j) & 1 else P0
+        if pattern == (1 << len(controls)) - 1:
+            f[t] = U
+        out += kron_all(f)
+    return out
 
 
 def gate_operator(W, gate, theta):
     kind, q0, q1 = gate[0], gate[1], gate[2]
+    q2 = gate[5] if len(gate) > 5 else -1
     if kind in ("RX", "RY", "RZ"):
         return expand_1q(W, q0, rotation(kind[1], theta))
     if kind in ("H", "X", "Y", "Z"):
@@ -67,8 +78,14 @@ def gate_operator(W, gate, theta):
         return expand_controlled(W, q0, q1, X)
     if kind == "CZ":
         return expand_controlled(W, q0, q1, Z)
-    if kind == "CRX":
-        return expand_controlled(W, q0, q1, rotation("X", theta))
+    if kind in ("CRX", "CRY", "CRZ"):
+        return expand_controlled(W, q0, q1, rotation(kind[2], theta))
+    if kind == "CCX":
+        return expand_multi_controlled(W, [q0, q1], q2, X)
+    if kind == "CCZ":
+        return expand_multi_controlled(W, [q0, q1], q2, Z)
+    if kind == "CCRX":
+        return expand_multi_controlled(W, [q0, q1], q2, rotation("X", theta))
     raise KeyError(kind)
 
 

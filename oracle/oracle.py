@@ -15,7 +15,8 @@ Gradient conventions:
   calls it a finite-difference approximation, but for gates exp(-i theta P/2)
   with P^2 = 1 it is exact): df/dtheta = [f(theta + pi/2) - f(theta - pi/2)] / 2.
   The generator of CRX, |1><1| (x) X, has eigenvalues {0, +-1}, so its angle
-  enters with two frequencies (1/2 and 1) and needs the four-term rule
+  enters with two frequencies (1/2 and 1) and needs the four-term rule (as do
+  CRY, CRZ and the doubly controlled CCRX)
   df = c+ [f(+pi/2) - f(-pi/2)] - c- [f(+3pi/2) - f(-3pi/2)],
   c+- = (sqrt(2) +- 1) / (4 sqrt(2)).
 """
@@ -34,7 +35,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # oracle-private gate numbering (must match the enum in qsv_oracle.c)
 KIND_CODE = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6,
-             "CNOT": 7, "CZ": 8, "CRX": 9}
+             "CNOT": 7, "CZ": 8, "CRX": 9, "CRY": 10, "CRZ": 11, "CCX": 12, "CCZ": 13,
+             "CCRX": 14}
+# kinds whose angle enters with two frequencies (a controlled rotation's
+# generator has eigenvalues 0 and +-1): four-term shift rule
+CONTROLLED_ROTATIONS = ("CRX", "CRY", "CRZ", "CCRX")
 SRC_CODE = {"none": 0, "weight": 1, "input": 2}
 
 _lib = None
@@ -59,10 +64,10 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         dp = ctypes.POINTER(ctypes.c_double)
         vp = ctypes.c_void_p
-        L.orc_forward.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, dp, ctypes.c_int,
+        L.orc_forward.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, ip, dp, ctypes.c_int,
                                   dp, ctypes.c_int, ctypes.c_int, dp, vp]
         L.orc_expval.argtypes = [ctypes.c_int, ctypes.c_int, vp, dp]
-        L.orc_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, dp, ctypes.c_int,
+        L.orc_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, ip, dp, ctypes.c_int,
                                   dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, vp]
         L.orc_gate_matrix.argtypes = [ctypes.c_int, ctypes.c_double, vp]
         for f in (L.orc_forward, L.orc_expval, L.orc_adjoint, L.orc_gate_matrix):
@@ -85,11 +90,12 @@ class _Gates:
         self.q1 = np.array([g[2] for g in gates], dtype=np.intc).reshape(self.n)
         self.src = np.array([SRC_CODE[g[3]] for g in gates], dtype=np.intc).reshape(self.n)
         self.idx = np.array([g[4] for g in gates], dtype=np.intc).reshape(self.n)
+        self.q2 = np.array([g[5] if len(g) > 5 else -1 for g in gates], dtype=np.intc).reshape(self.n)
 
     def args(self):
         ip = ctypes.c_int
         return (self.n, _ptr(self.kind, ip), _ptr(self.q0, ip), _ptr(self.q1, ip),
-                _ptr(self.src, ip), _ptr(self.idx, ip))
+                _ptr(self.src, ip), _ptr(self.idx, ip), _ptr(self.q2, ip))
 
 
 def _prep(weights, inputs, batch, n_inputs):
@@ -149,7 +155,7 @@ def adjoint(n_qubits, gates, weights, inputs, batch, grad_out, want_state=False)
 
 
 def gate_matrix(kind, theta=0.0):
-    """The oracle's own 2x2 matrix for a gate kind (target part for CNOT/CZ/CRX)."""
+    """The oracle's own 2x2 matrix for a gate kind (the target part of a controlled kind)."""
     out = np.empty(4, dtype=np.complex128)
     if lib().orc_gate_matrix(KIND_CODE[kind], float(theta), out.ctypes.data):
         raise ValueError(kind)
@@ -191,7 +197,7 @@ def _gate_shift_derivative(n_qubits, gates, weights, inputs, batch, grad_out, k)
         sh[k] = delta
         return loss(n_qubits, gates, weights, inputs, batch, grad_out, sh)
 
-    if gates[k][0] == "CRX":
+    if gates[k][0] in CONTROLLED_ROTATIONS:
         h1, h3 = math.pi / 2, 3 * math.pi / 2
         return _CP * (L(h1) - L(-h1)) - _CM * (L(h3) - L(-h3))
     return 0.5 * (L(math.pi / 2) - L(-math.pi / 2))

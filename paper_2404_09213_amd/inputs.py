@@ -4,14 +4,17 @@ This module holds no simulation arithmetic. It only writes down gate lists and
 draws random angles, so that the oracle and the HIP path can be fed identical
 inputs. It imports nothing but numpy.
 
-A gate is a tuple ``(kind, q0, q1, src, idx)``:
+A gate is a tuple ``(kind, q0, q1, src, idx)``, or ``(kind, q0, q1, src, idx,
+q2)`` for the three-qubit kinds:
 
-* ``kind``  one of ``H X Y Z RX RY RZ CNOT CZ CRX``;
-* ``q0``    the qubit of a 1-qubit gate, or the control of a 2-qubit gate;
-* ``q1``    the target of a 2-qubit gate, ``-1`` for 1-qubit gates;
+* ``kind``  one of ``H X Y Z RX RY RZ CNOT CZ CRX CRY CRZ CCX CCZ CCRX``;
+* ``q0``    the qubit of a 1-qubit gate, or the first control;
+* ``q1``    the target of a 1-control gate, the second control of a 2-control
+            gate, ``-1`` for 1-qubit gates;
 * ``src``   ``"none"`` (fixed gate), ``"weight"`` (angle = weights[idx]) or
             ``"input"`` (angle = inputs[b, idx], one per batch sample);
-* ``idx``   index into the weight vector or the input row, ``-1`` if none.
+* ``idx``   index into the weight vector or the input row, ``-1`` if none;
+* ``q2``    the target of a 2-control gate (absent or ``-1`` otherwise).
 
 Qubit 0 is the most significant bit of a basis-state index (the MSb-0
 convention of the paper's preliminaries, section "Symbols").
@@ -29,8 +32,16 @@ import math
 import numpy as np
 
 KINDS = ("H", "X", "Y", "Z", "RX", "RY", "RZ", "CNOT", "CZ", "CRX")
-PARAMETRIC = ("RX", "RY", "RZ", "CRX")
-TWO_QUBIT = ("CNOT", "CZ", "CRX")
+CONTROLLED_KINDS = ("CRY", "CRZ", "CCX", "CCZ", "CCRX")
+ALL_KINDS = KINDS + CONTROLLED_KINDS
+PARAMETRIC = ("RX", "RY", "RZ", "CRX", "CRY", "CRZ", "CCRX")
+TWO_QUBIT = ("CNOT", "CZ", "CRX", "CRY", "CRZ")
+THREE_QUBIT = ("CCX", "CCZ", "CCRX")
+
+
+def gate_q2(g):
+    """Third qubit of a gate tuple (-1 when the gate has fewer qubits)."""
+    return g[5] if len(g) > 5 else -1
 
 
 @dataclass
@@ -42,15 +53,19 @@ class Circuit:
     name: str = ""
 
     # -- construction helpers -------------------------------------------------
-    def fixed(self, kind, q0, q1=-1):
-        self.gates.append((kind, int(q0), int(q1), "none", -1))
+    def _add(self, kind, q0, q1, src, idx, q2):
+        g = (kind, int(q0), int(q1), src, int(idx))
+        self.gates.append(g + (int(q2),) if q2 >= 0 else g)
 
-    def weight(self, kind, q0, q1=-1):
-        self.gates.append((kind, int(q0), int(q1), "weight", self.n_weights))
+    def fixed(self, kind, q0, q1=-1, q2=-1):
+        self._add(kind, q0, q1, "none", -1, q2)
+
+    def weight(self, kind, q0, q1=-1, q2=-1):
+        self._add(kind, q0, q1, "weight", self.n_weights, q2)
         self.n_weights += 1
 
-    def input(self, kind, q0, col, q1=-1):
-        self.gates.append((kind, int(q0), int(q1), "input", int(col)))
+    def input(self, kind, q0, col, q1=-1, q2=-1):
+        self._add(kind, q0, q1, "input", int(col), q2)
         self.n_inputs = max(self.n_inputs, int(col) + 1)
 
     def arrays(self):
@@ -61,8 +76,9 @@ class Circuit:
         src = np.array([{"none": 0, "weight": 1, "input": 2}[g[3]] for g in self.gates],
                        dtype=np.int32).reshape(n)
         idx = np.array([g[4] for g in self.gates], dtype=np.int32).reshape(n)
+        q2 = np.array([gate_q2(g) for g in self.gates], dtype=np.int32).reshape(n)
         kinds = [g[0] for g in self.gates]
-        return kinds, q0, q1, src, idx
+        return kinds, q0, q1, src, idx, q2
 
 
 # -- circuit families ----------------------------------------------------------
@@ -133,8 +149,9 @@ def random_layers(n_qubits: int, layers: int, rng: np.random.Generator) -> Circu
 
 
 def random_mixed(n_qubits: int, n_gates: int, rng: np.random.Generator,
-                 n_inputs: int = 0, p_input: float = 0.0) -> Circuit:
-    """A random gate list over every kind, every qubit and every ordered pair.
+                 n_inputs: int = 0, p_input: float = 0.0, kinds=KINDS) -> Circuit:
+    """A random gate list over the given kinds, every qubit and every ordered
+    pair or triple of qubits.
 
     Used for small-size parity and pin tests. When `n_inputs` > 0, a fraction
     `p_input` of the parametric gates reads a per-sample input column instead
@@ -142,21 +159,25 @@ def random_mixed(n_qubits: int, n_gates: int, rng: np.random.Generator,
     """
     c = Circuit(n_qubits, name=f"random_mixed_w{n_qubits}_g{n_gates}")
     for _ in range(n_gates):
-        k = KINDS[int(rng.integers(len(KINDS)))]
-        if k in TWO_QUBIT and n_qubits < 2:
+        k = kinds[int(rng.integers(len(kinds)))]
+        if (k in TWO_QUBIT and n_qubits < 2) or (k in THREE_QUBIT and n_qubits < 3):
             k = "RY"
-        if k in TWO_QUBIT:
+        q2 = -1
+        if k in THREE_QUBIT:
+            a, b, t = rng.choice(n_qubits, size=3, replace=False)
+            q0, q1, q2 = int(a), int(b), int(t)
+        elif k in TWO_QUBIT:
             a, b = rng.choice(n_qubits, size=2, replace=False)
             q0, q1 = int(a), int(b)
         else:
             q0, q1 = int(rng.integers(n_qubits)), -1
         if k in PARAMETRIC:
             if n_inputs > 0 and rng.random() < p_input:
-                c.input(k, q0, int(rng.integers(n_inputs)), q1)
+                c.input(k, q0, int(rng.integers(n_inputs)), q1, q2)
             else:
-                c.weight(k, q0, q1)
+                c.weight(k, q0, q1, q2)
         else:
-            c.fixed(k, q0, q1)
+            c.fixed(k, q0, q1, q2)
     c.n_inputs = max(c.n_inputs, n_inputs)
     return c
 

@@ -7,6 +7,7 @@ Sources of truth used here: the paper's worked examples (MSb-0 ordering in
 a classical bit-level simulation of permutation circuits, and exact
 shift-rule / finite-difference gradients.
 """
+import itertools
 import math
 
 import numpy as np
@@ -395,3 +396,91 @@ def test_remapped_adjoint_vs_fd(orc):
     # input gradients are unchanged by the remap (it acts on weights only)
     gw0, gx0 = orc.adjoint(W, c.gates, orc.remap(w64), x64, B, g)
     assert np.array_equal(gx, gx0)
+
+
+# -- multi-qubit gates: CRY, CRZ, Toffoli (CCX), CCZ, CCRX (section "Conclusion") --
+
+def _x_prep(W, bits):
+    """X on every qubit whose bit is 1: prepares the basis state `bits`."""
+    return [("X", q, -1, "none", -1) for q in range(W) if (bits >> (W - 1 - q)) & 1]
+
+
+@pytest.mark.parametrize("order", [(0, 1, 2), (2, 0, 1), (1, 2, 0)])
+def test_toffoli_truth_table(orc, order):
+    W = 3
+    c0, c1, t = order
+    for bits in range(8):
+        gates = _x_prep(W, bits) + [("CCX", c0, c1, "none", -1, t)]
+        st = run(orc, W, gates, np.zeros(0))
+        b = [(bits >> (W - 1 - q)) & 1 for q in range(W)]
+        if b[c0] and b[c1]:
+            b[t] ^= 1
+        want = sum(v << (W - 1 - q) for q, v in enumerate(b))
+        assert abs(st[0, want] - 1) < 1e-15 and np.count_nonzero(np.abs(st[0]) > 1e-15) == 1
+
+
+def test_ccz_phase_only_on_all_ones(orc):
+    W = 4
+    gates = [("H", q, -1, "none", -1) for q in range(W)] + [("CCZ", 3, 0, "none", -1, 2)]
+    st = run(orc, W, gates, np.zeros(0))[0]
+    for i in range(16):
+        sign = -1 if (i >> 3) & 1 and (i >> 0) & 1 and (i >> 1) & 1 else 1  # qubits 0, 2, 3
+        assert abs(st[i] - sign * 0.25) < 1e-15
+
+
+def _controlled_kinds_vs_kron(orc, W, kinds, rng):
+    for kind in kinds:
+        nq = 3 if kind.startswith("CC") else 2
+        for qs in itertools.permutations(range(W), nq):
+            prep = I.random_mixed(W, 10, rng)
+            w = list(rng.uniform(0, 2 * math.pi, size=prep.n_weights))
+            theta = float(rng.uniform(0, 2 * math.pi))
+            param = kind in ("CRY", "CRZ", "CCRX")
+            if nq == 2:
+                g = (kind, qs[0], qs[1], "weight" if param else "none", len(w) if param else -1)
+            else:
+                g = (kind, qs[0], qs[1], "weight" if param else "none", len(w) if param else -1, qs[2])
+            w64 = np.array(w + [theta])
+            gates = prep.gates + [g]
+            got = run(orc, W, gates, w64)
+            ref = kron.states(W, gates, w64, None, 1)
+            assert np.max(np.abs(got - ref)) < 1e-12, (kind, qs)
+
+
+def test_controlled_kinds_every_placement_vs_kron(orc):
+    rng = np.random.default_rng(17)
+    _controlled_kinds_vs_kron(orc, 3, ("CRY", "CRZ", "CCX", "CCZ", "CCRX"), rng)
+    _controlled_kinds_vs_kron(orc, 4, ("CRY", "CRZ", "CCX", "CCZ", "CCRX"), rng)
+
+
+@pytest.mark.parametrize("W,seed", [(4, 31), (6, 32)])
+def test_random_circuits_with_controlled_kinds_vs_kron(orc, W, seed):
+    rng = np.random.default_rng(seed)
+    c = I.random_mixed(W, 50, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS)
+    w, x = I.draw_angles(c, 2, seed)
+    got = run(orc, W, c.gates, w.astype(np.float64), x.astype(np.float64), 2)
+    ref = kron.states(W, c.gates, w.astype(np.float64), x.astype(np.float64), 2)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    assert np.max(np.abs(orc.expval(W, got) - kron.expval(W, ref))) < 1e-12
+
+
+@pytest.mark.parametrize("W,seed", [(3, 41), (5, 42)])
+def test_controlled_rotations_adjoint_vs_four_term_vs_fd(orc, W, seed):
+    """Controlled rotations (generator eigenvalues 0, +-1) need the four-term
+    rule; the adjoint generator is the target's Pauli where all controls are 1."""
+    rng = np.random.default_rng(seed)
+    c = I.random_mixed(W, 30, rng, n_inputs=2, p_input=0.25, kinds=I.ALL_KINDS)
+    assert any(g[0] in ("CRY", "CRZ", "CCRX") for g in c.gates)
+    B = 2
+    w, x = I.draw_angles(c, B, seed)
+    w64, x64 = w.astype(np.float64), x.astype(np.float64)
+    g = I.draw_grad_out(c, B, seed)
+    gw, gx = orc.adjoint(W, c.gates, w64, x64, B, g)
+    sw, sx = orc.param_shift(W, c.gates, w64, x64, B, g)
+    fw, fx = orc.finite_diff(W, c.gates, w64, x64, B, g)
+    for j in range(c.n_weights):
+        assert abs(gw[j] - sw[j]) < 1e-10, (j, gw[j], sw[j])
+        assert abs(gw[j] - fw[j]) < 1e-6
+    for j in range(c.n_inputs):
+        assert np.max(np.abs(gx[:, j] - sx[j])) < 1e-10
+        assert np.max(np.abs(gx[:, j] - fx[j])) < 1e-6
