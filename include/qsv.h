@@ -51,11 +51,18 @@
 extern "C" {
 #endif
 
-/* gate kinds */
+/* gate kinds. Controlled kinds list their controls first: q0 for one
+ * control (target q1), q0 and q1 for two controls (target q2). The target
+ * part of a controlled kind is the gate of the same letter: CRY(c,t) applies
+ * RY to t where c = 1, CRZ likewise, CCX (Toffoli) flips t where both
+ * controls are 1, CCZ negates where all three qubits are 1, CCRX applies RX
+ * to t where both controls are 1 (multi-controlled gates, named as future
+ * work in section "Conclusion"). */
 enum {
     QSV_H = 0, QSV_X = 1, QSV_Y = 2, QSV_Z = 3,
     QSV_RX = 4, QSV_RY = 5, QSV_RZ = 6,
-    QSV_CNOT = 7, QSV_CZ = 8, QSV_CRX = 9
+    QSV_CNOT = 7, QSV_CZ = 8, QSV_CRX = 9,
+    QSV_CRY = 10, QSV_CRZ = 11, QSV_CCX = 12, QSV_CCZ = 13, QSV_CCRX = 14
 };
 
 /* where a gate's angle comes from */
@@ -65,7 +72,7 @@ enum { QSV_SRC_NONE = 0, QSV_SRC_WEIGHT = 1, QSV_SRC_INPUT = 2 };
 enum {
     QSV_OK = 0,
     QSV_ERR_ARG = -1,      /* null pointer, batch <= 0, workspace too small, bad option */
-    QSV_ERR_QUBIT = -2,    /* qubit index out of range, or a 2-qubit gate on one qubit */
+    QSV_ERR_QUBIT = -2,    /* qubit index out of range, or a gate naming one qubit twice */
     QSV_ERR_GATE = -3,     /* unknown gate kind */
     QSV_ERR_PARAM = -4,    /* angle source / index invalid for the gate */
     QSV_ERR_TOO_BIG = -5,  /* W > QSV_MAX_QUBITS or the state size overflows */
@@ -86,11 +93,13 @@ enum {
 enum { QSV_OP_FORWARD = 0, QSV_OP_EXPVAL = 1, QSV_OP_BACKWARD = 2, QSV_OP_STEP = 3 };
 
 typedef struct {
-    int32_t kind;  /* QSV_H ... QSV_CRX */
-    int32_t q0;    /* qubit (1-qubit gates) or control (2-qubit gates) */
-    int32_t q1;    /* target of a 2-qubit gate; -1 for 1-qubit gates */
+    int32_t kind;  /* QSV_H ... QSV_CCRX */
+    int32_t q0;    /* qubit (1-qubit gates) or first control */
+    int32_t q1;    /* target of a 1-control gate, second control of a 2-control
+                      gate; -1 for 1-qubit gates */
     int32_t src;   /* QSV_SRC_NONE | QSV_SRC_WEIGHT | QSV_SRC_INPUT */
     int32_t idx;   /* weights[idx] or inputs[b * n_inputs + idx]; -1 if src is NONE */
+    int32_t q2;    /* target of a 2-control gate; -1 otherwise */
 } qsv_gate;
 
 typedef struct {

@@ -19,7 +19,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqsv.so")
 
-KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "CZ": 8, "CRX": 9}
+KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "CZ": 8, "CRX": 9,
+        "CRY": 10, "CRZ": 11, "CCX": 12, "CCZ": 13, "CCRX": 14}
 SRC = {"none": 0, "weight": 1, "input": 2}
 METHOD = {"fused": 0, "per_gate": 1}
 OP_FORWARD, OP_EXPVAL, OP_BACKWARD, OP_STEP = 0, 1, 2, 3
@@ -37,7 +38,7 @@ class QsvError(RuntimeError):
 
 class qsv_gate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
-                ("src", ctypes.c_int32), ("idx", ctypes.c_int32)]
+                ("src", ctypes.c_int32), ("idx", ctypes.c_int32), ("q2", ctypes.c_int32)]
 
 
 class qsv_opts(ctypes.Structure):
@@ -155,12 +156,9 @@ def qsv_default_opts():
 
 
 def qsv_plan(n_qubits, gates, n_weights, n_inputs, opts=None):
-    """gates: sequence of (kind, q0, q1, src, idx) with kind/src as names or codes."""
+    """gates: sequence of (kind, q0, q1, src, idx[, q2]) with kind/src as names or codes."""
     n = len(gates)
-    arr = (qsv_gate * max(n, 1))()
-    for i, (k, q0, q1, s, idx) in enumerate(gates):
-        arr[i] = qsv_gate(KIND[k] if isinstance(k, str) else int(k), int(q0), int(q1),
-                          SRC[s] if isinstance(s, str) else int(s), int(idx))
+    arr = _gate_array(gates)
     h = ctypes.c_void_p()
     _check(lib().qsv_plan(int(n_qubits), arr, n, int(n_weights), int(n_inputs),
                           ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
@@ -170,9 +168,11 @@ def qsv_plan(n_qubits, gates, n_weights, n_inputs, opts=None):
 def _gate_array(gates):
     n = len(gates)
     arr = (qsv_gate * max(n, 1))()
-    for i, (k, q0, q1, s, idx) in enumerate(gates):
+    for i, g in enumerate(gates):
+        k, q0, q1, s, idx = g[:5]
+        q2 = g[5] if len(g) > 5 else -1
         arr[i] = qsv_gate(KIND[k] if isinstance(k, str) else int(k), int(q0), int(q1),
-                          SRC[s] if isinstance(s, str) else int(s), int(idx))
+                          SRC[s] if isinstance(s, str) else int(s), int(idx), int(q2))
     return arr
 
 

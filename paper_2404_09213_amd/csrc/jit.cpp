@@ -185,7 +185,8 @@ private:
     // execution mask), i.e. not under a control outside the registers.
     // opts.mfma bits: 1 forward kernels, 2 backward psi array, 4 backward lambda array.
     bool use_mfma(const DOp& op) const {
-        return (p_->opts.mfma & (bwd_ ? 6 : 1)) && op.kind == OP_U2 && op.ctl < kCtlNonReg;
+        return (p_->opts.mfma & (bwd_ ? 6 : 1)) && op.kind == OP_U2 && op.ctl < kCtlNonReg &&
+               op.ctl2 < kCtlNonReg;
     }
     bool mfma_array(const std::string& A) const {
         if (!bwd_) return p_->opts.mfma & 1;
@@ -285,11 +286,24 @@ private:
 
     // pairs (k, k | 1<<pos) of an op on register position `pos`; with a control
     // on a register position, only pairs where that bit is 1.
-    std::vector<int> pairs(int pos, int ctl) const {
+    // register k satisfies the op's controls that sit on register positions
+    static bool reg_ok(const DOp& op, int k) {
+        for (int c : {op.ctl, op.ctl2})
+            if (c >= 0 && c < kCtlNonReg && !(k >> c & 1)) return false;
+        return true;
+    }
+    // run-time condition of the op's controls outside the registers ("" if none)
+    static std::string nonreg_cond(const DOp& op) {
+        std::string c;
+        for (int x : {op.ctl, op.ctl2})
+            if (x >= kCtlNonReg) c += std::string(c.empty() ? "" : " && ") + "((gT >> " + I(x & 0xFF) + ") & 1)";
+        return c;
+    }
+    std::vector<int> pairs(const DOp& op) const {
         std::vector<int> v;
         for (int k = 0; k < kRegs; ++k) {
-            if (k >> pos & 1) continue;
-            if (ctl >= 0 && ctl < kCtlNonReg && !(k >> ctl & 1)) continue;
+            if (k >> op.pos & 1) continue;
+            if (!reg_ok(op, k)) continue;
             v.push_back(k);
         }
         return v;
@@ -304,7 +318,7 @@ private:
         std::vector<std::pair<std::string, std::string>> xy;
         for (const std::string& A : arrays_)
             if (mfma_array(A))
-                for (int k : pairs(op.pos, op.ctl)) xy.emplace_back(rk(A, k), rk(A, k | (1 << op.pos)));
+                for (int k : pairs(op)) xy.emplace_back(rk(A, k), rk(A, k | (1 << op.pos)));
         const int n = (int)xy.size();
         o_ << "    {\n";
         for (int i = 0; i < n; ++i)
@@ -323,7 +337,7 @@ private:
     }
 
     void emit_pair_op(const DOp& op, const std::string& A) {
-        for (int k : pairs(op.pos, op.ctl)) {
+        for (int k : pairs(op)) {
             const int k1 = k | (1 << op.pos);
             const std::string x = rk(A, k), y = rk(A, k1);
             o_ << "      { const f2 x = " << x << ", y = " << y << ";\n";
@@ -359,10 +373,10 @@ private:
                 o_ << "    int f_ = 0;\n";
                 for (int i = 0; i < nt; ++i) {
                     const DTerm& tm = p_->terms[op.term0 + i];
-                    if (tm.s1 < 0)
-                        o_ << "    if ((gT >> " << tm.s0 << ") & 1) f_ ^= " << hex(tm.mask) << ";\n";
-                    else
-                        o_ << "    if ((gT >> " << tm.s0 << ") & (gT >> " << tm.s1 << ") & 1) f_ ^= 0xffff;\n";
+                    std::string c = "(gT >> " + I(tm.s0) + ")";
+                    if (tm.s1 >= 0) c += " & (gT >> " + I(tm.s1) + ")";
+                    if (tm.s2 >= 0) c += " & (gT >> " + I(tm.s2) + ")";
+                    o_ << "    if ((" << c << ") & 1) f_ ^= " << hex(tm.mask) << ";\n";
                 }
             }
             for (const std::string& A : arrays_)
@@ -379,9 +393,12 @@ private:
             return;
         }
         if (op.kind == OP_DIAG) {
+            const std::string nc = nonreg_cond(op);
+            if (!nc.empty()) o_ << "    if (" << nc << ") {\n";
             if (op.pos >= 0) {
                 for (const std::string& A : arrays_)
                     for (int k = 0; k < kRegs; ++k) {
+                        if (!reg_ok(op, k)) continue;
                         const bool hi = k >> op.pos & 1;
                         const std::string pr = hi ? "m3r" : "m0r", pi = hi ? "m3i" : "m0i";
                         o_ << "    { const f2 x = " << rk(A, k) << "; " << rk(A, k) << " = make_float2(" << pr
@@ -391,19 +408,22 @@ private:
                 o_ << "    const bool hb_ = (gT >> " << op.sh << ") & 1;\n"
                    << "    const float pr = hb_ ? m3r : m0r, pi = hb_ ? m3i : m0i;\n";
                 for (const std::string& A : arrays_)
-                    for (int k = 0; k < kRegs; ++k)
+                    for (int k = 0; k < kRegs; ++k) {
+                        if (!reg_ok(op, k)) continue;
                         o_ << "    { const f2 x = " << rk(A, k) << "; " << rk(A, k)
                            << " = make_float2(pr * x.x - pi * x.y, pr * x.y + pi * x.x); }\n";
+                    }
             }
+            if (!nc.empty()) o_ << "    }\n";
             o_ << "  }\n";
             return;
         }
-        const bool nonreg_ctl = op.ctl >= kCtlNonReg;
-        if (nonreg_ctl) o_ << "    if ((gT >> " << (op.ctl & 0xFF) << ") & 1) {\n";
+        const std::string nc = nonreg_cond(op);
+        if (!nc.empty()) o_ << "    if (" << nc << ") {\n";
         if (use_mfma(op)) emit_pairs_mfma(op);
         for (const std::string& A : arrays_)
             if (!use_mfma(op) || !mfma_array(A)) emit_pair_op(op, A);
-        if (nonreg_ctl) o_ << "    }\n";
+        if (!nc.empty()) o_ << "    }\n";
         o_ << "  }\n";
     }
 
@@ -412,18 +432,23 @@ private:
         const std::string gs = "g" + I(op.slot);
         const std::string g = "ga_";
         o_ << "  {\n    float ga_ = 0.f, gb_ = 0.f;\n";
-        const bool nonreg_ctl = op.ctl >= kCtlNonReg;
+        const std::string nc = nonreg_cond(op);
         if (op.kind == OP_GZ && op.pos < 0) {
             o_ << "    float h_ = 0.f;\n";
-            for (int k = 0; k < kRegs; ++k)
+            if (!nc.empty()) o_ << "    if (" << nc << ") {\n";
+            for (int k = 0; k < kRegs; ++k) {
+                if (!reg_ok(op, k)) continue;
                 o_ << "    h_ = fmaf(lm[" << k << "].x, ps[" << k << "].y, h_); h_ = fmaf(-lm[" << k
                    << "].y, ps[" << k << "].x, h_);\n";
+            }
+            if (!nc.empty()) o_ << "    }\n";
             o_ << "    " << gs << " = ((gT >> " << op.sh << ") & 1) ? -h_ : h_;\n  }\n";
             return;
         }
-        if (nonreg_ctl) o_ << "    if ((gT >> " << (op.ctl & 0xFF) << ") & 1) {\n";
+        if (!nc.empty()) o_ << "    if (" << nc << ") {\n";
         if (op.kind == OP_GZ) {
             for (int k = 0; k < kRegs; ++k) {
+                if (!reg_ok(op, k)) continue;
                 const std::string g = (k & 1) ? "gb_" : "ga_";
                 const char* sg = (k >> op.pos & 1) ? "-" : "";
                 o_ << "    " << g << " = fmaf(" << sg << "lm[" << k << "].x, ps[" << k << "].y, " << g << "); "
@@ -432,7 +457,7 @@ private:
             }
         } else {
             int alt = 0;
-            for (int k : pairs(op.pos, op.ctl)) {
+            for (int k : pairs(op)) {
                 const std::string g = (alt++ & 1) ? "gb_" : "ga_";
                 const int k1 = k | (1 << op.pos);
                 const std::string l0 = rk("lm", k), l1 = rk("lm", k1), p0 = rk("ps", k), p1 = rk("ps", k1);
@@ -446,7 +471,7 @@ private:
                        << ".x, " << g << "); " << g << " = fmaf(-" << l0 << ".y, " << p1 << ".y, " << g << ");\n";
             }
         }
-        if (nonreg_ctl) o_ << "    }\n";
+        if (!nc.empty()) o_ << "    }\n";
         o_ << "    " << gs << " = ga_ + gb_;\n  }\n";
     }
 

@@ -54,19 +54,22 @@ constexpr int32_t kCtlNonReg = 0x100;
 struct DOp {
     int32_t kind;
     int32_t pos;      // register position of the target, or -1
-    int32_t ctl;      // control, see above
+    int32_t ctl;      // first control, see above (-1 none)
     int32_t mat;      // matrix slot (>= 0 shared, < 0 per-sample: -mat-1)
     int32_t slot;     // local gradient slot within the pass (OP_G*)
     int32_t sh;       // global bit shift for non-register diagonal / GZ ops
     int32_t term0;    // OP_SIGN: first term
     int32_t nterm;    // OP_SIGN: number of terms; uniform 16-bit mask in `pos`
+    int32_t ctl2;     // second control, same encoding (-1 none)
+    int32_t pad;
 };
 
-// Sign term of an OP_SIGN group, for one stage layout:
-//  s1 <  0: if bit s0 of the thread's global index is set, flip `mask` registers;
-//  s1 >= 0: if bits s0 and s1 are both set, flip all registers.
+// Sign term of an OP_SIGN group, for one stage layout: if every listed bit
+// (s0, s1, s2; -1 = unused) of the thread's global index is set, flip the
+// registers in `mask`. A CZ / CCZ contributes its register-only part to the
+// op's uniform mask and its other qubits as a term.
 struct DTerm {
-    int32_t s0, s1, mask, pad;
+    int32_t s0, s1, s2, mask;
 };
 
 struct DStage {
@@ -114,11 +117,13 @@ struct DGOut {
 struct PGate {
     int32_t gate;       // gate index
     int32_t cls;        // OpKind of the apply step (U2/REAL/RXL/DIAG/SIGN/SWAP)
-    int32_t tsh, csh;   // target / control global shifts (-1 none)
+    int32_t tsh, csh;   // target / first control global shifts (-1 none)
     int32_t mat;        // matrix slot
     int32_t grad;       // OP_GX/GY/GZ or -1
     int32_t slot;       // parametric gate ordinal or -1
-    int32_t sh2;        // CZ second shift
+    int32_t sh2;        // OP_SIGN: second qubit's shift
+    int32_t csh2;       // second control shift (OP_SIGN: third qubit of a CCZ), -1 none
+    int32_t pad;
 };
 
 // One circuit of a multi-circuit plan.

@@ -37,19 +37,38 @@ namespace {
 
 inline int popc(uint32_t x) { return __builtin_popcount(x); }
 
-bool is_two(int k) { return k == QSV_CNOT || k == QSV_CZ || k == QSV_CRX; }
-bool is_param_kind(int k) { return k == QSV_RX || k == QSV_RY || k == QSV_RZ || k == QSV_CRX; }
+// Controls of a kind (listed first: q0, then q1); the target follows them.
+int n_ctl(int k) {
+    switch (k) {
+    case QSV_CNOT: case QSV_CZ: case QSV_CRX: case QSV_CRY: case QSV_CRZ: return 1;
+    case QSV_CCX: case QSV_CCZ: case QSV_CCRX: return 2;
+    default: return 0;
+    }
+}
+bool is_multi(int k) { return n_ctl(k) > 0; }
+int target_of(const qsv_gate& g) { return n_ctl(g.kind) == 0 ? g.q0 : n_ctl(g.kind) == 1 ? g.q1 : g.q2; }
+bool is_param_kind(int k) {
+    return k == QSV_RX || k == QSV_RY || k == QSV_RZ || k == QSV_CRX || k == QSV_CRY || k == QSV_CRZ ||
+           k == QSV_CCRX;
+}
+bool is_zz(int k) { return k == QSV_CZ || k == QSV_CCZ; }  // pure sign flips
 
 uint32_t qmask(const qsv_gate& g) {
-    return (1u << g.q0) | (is_two(g.kind) ? (1u << g.q1) : 0u);
+    uint32_t m = 1u << g.q0;
+    if (n_ctl(g.kind) >= 1) m |= 1u << g.q1;
+    if (n_ctl(g.kind) >= 2) m |= 1u << g.q2;
+    return m;
 }
 
 // Dense (D) and diagonal/control (C) qubit masks of a gate.
 void gate_sets(const qsv_gate& g, uint32_t& D, uint32_t& C) {
     switch (g.kind) {
     case QSV_Z: case QSV_RZ: D = 0; C = 1u << g.q0; break;
-    case QSV_CZ: D = 0; C = (1u << g.q0) | (1u << g.q1); break;
-    case QSV_CNOT: case QSV_CRX: D = 1u << g.q1; C = 1u << g.q0; break;
+    case QSV_CZ: case QSV_CCZ: case QSV_CRZ: D = 0; C = qmask(g); break;
+    case QSV_CNOT: case QSV_CRX: case QSV_CRY: case QSV_CCX: case QSV_CCRX:
+        D = 1u << target_of(g);
+        C = qmask(g) & ~D;
+        break;
     default: D = 1u << g.q0; C = 0; break;
     }
 }
@@ -71,16 +90,16 @@ void fill_partials(DGate& d, const qsv_gate& g) {
     const double r = 1.0 / std::sqrt(2.0);
     switch (g.kind) {
     case QSV_H: setm(d.C, 0, 0, r, 0); setm(d.C, 0, 1, r, 0); setm(d.C, 1, 0, r, 0); setm(d.C, 1, 1, -r, 0); break;
-    case QSV_X: case QSV_CNOT: setm(d.C, 0, 1, 1, 0); setm(d.C, 1, 0, 1, 0); break;
+    case QSV_X: case QSV_CNOT: case QSV_CCX: setm(d.C, 0, 1, 1, 0); setm(d.C, 1, 0, 1, 0); break;
     case QSV_Y: setm(d.C, 0, 1, 0, -1); setm(d.C, 1, 0, 0, 1); break;
-    case QSV_Z: case QSV_CZ: setm(d.C, 0, 0, 1, 0); setm(d.C, 1, 1, -1, 0); break;
-    case QSV_RX: case QSV_CRX:  // cos I + sin (-i X)
+    case QSV_Z: case QSV_CZ: case QSV_CCZ: setm(d.C, 0, 0, 1, 0); setm(d.C, 1, 1, -1, 0); break;
+    case QSV_RX: case QSV_CRX: case QSV_CCRX:  // cos I + sin (-i X)
         setm(d.A, 0, 0, 1, 0); setm(d.A, 1, 1, 1, 0);
         setm(d.S, 0, 1, 0, -1); setm(d.S, 1, 0, 0, -1); break;
-    case QSV_RY:  // cos I + sin [[0,-1],[1,0]]
+    case QSV_RY: case QSV_CRY:  // cos I + sin [[0,-1],[1,0]]
         setm(d.A, 0, 0, 1, 0); setm(d.A, 1, 1, 1, 0);
         setm(d.S, 0, 1, -1, 0); setm(d.S, 1, 0, 1, 0); break;
-    case QSV_RZ:  // cos I + sin (-i Z)
+    case QSV_RZ: case QSV_CRZ:  // cos I + sin (-i Z)
         setm(d.A, 0, 0, 1, 0); setm(d.A, 1, 1, 1, 0);
         setm(d.S, 0, 0, 0, -1); setm(d.S, 1, 1, 0, 1); break;
     }
@@ -91,15 +110,16 @@ int recipe_class(const qsv_plan_t* p, const std::vector<int>& gs) {
     bool all_diag = true, all_real = true;
     for (int g : gs) {
         const int k = p->gates[g].kind;
-        if (!(k == QSV_Z || k == QSV_RZ || k == QSV_CZ)) all_diag = false;
-        if (!(k == QSV_H || k == QSV_X || k == QSV_Z || k == QSV_RY || k == QSV_CNOT || k == QSV_CZ))
+        if (!(k == QSV_Z || k == QSV_RZ || k == QSV_CZ || k == QSV_CRZ || k == QSV_CCZ)) all_diag = false;
+        if (!(k == QSV_H || k == QSV_X || k == QSV_Z || k == QSV_RY || k == QSV_CNOT || k == QSV_CZ ||
+              k == QSV_CRY || k == QSV_CCX || k == QSV_CCZ))
             all_real = false;
     }
     if (all_diag) return OP_DIAG;
     if (gs.size() == 1) {
         const int k = p->gates[gs[0]].kind;
-        if (k == QSV_X || k == QSV_CNOT) return OP_SWAP;
-        if (k == QSV_RX || k == QSV_CRX) return OP_RXL;
+        if (k == QSV_X || k == QSV_CNOT || k == QSV_CCX) return OP_SWAP;
+        if (k == QSV_RX || k == QSV_CRX || k == QSV_CCRX) return OP_RXL;
     }
     return all_real ? OP_REAL : OP_U2;
 }
@@ -250,7 +270,7 @@ std::vector<Unit> fwd_units(const qsv_plan_t* p, const std::vector<int>& gates) 
     std::vector<int> open(p->W, -1);
     for (int g : gates) {
         const qsv_gate& G = p->gates[g];
-        if (!is_two(G.kind)) {
+        if (!is_multi(G.kind)) {
             int& u = open[G.q0];
             if (u < 0) {
                 units.emplace_back();
@@ -263,11 +283,12 @@ std::vector<Unit> fwd_units(const qsv_plan_t* p, const std::vector<int>& gates) 
             units[u].D |= D;
             units[u].C |= C;
         } else {
-            open[G.q0] = open[G.q1] = -1;
+            for (int q = 0; q < p->W; ++q)
+                if (qmask(G) >> q & 1) open[q] = -1;
             Unit x;
             x.gates.push_back(g);
             gate_sets(G, x.D, x.C);
-            x.qubit = G.q1;
+            x.qubit = target_of(G);
             units.push_back(x);
         }
     }
@@ -291,7 +312,7 @@ std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates, 
         const qsv_gate& G = p->gates[g];
         uint32_t D, C;
         gate_sets(G, D, C);
-        if (!is_two(G.kind)) {
+        if (!is_multi(G.kind)) {
             int& u = open[G.q0];
             if (u < 0) {
                 chains.emplace_back();
@@ -302,12 +323,13 @@ std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates, 
             chains[u].D |= D;
             chains[u].C |= C;
         } else {
-            open[G.q0] = open[G.q1] = -1;
+            for (int q = 0; q < p->W; ++q)
+                if (qmask(G) >> q & 1) open[q] = -1;
             Unit x;
             x.gates.push_back(g);
             x.D = D;
             x.C = C;
-            x.qubit = G.q1;
+            x.qubit = target_of(G);
             chains.push_back(x);
         }
     }
@@ -316,7 +338,7 @@ std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates, 
         u.C &= ~u.D;
         const int n = (int)u.gates.size();
         bool fused = false;
-        if (fuse && n >= 2 && !is_two(p->gates[u.gates[0]].kind)) {
+        if (fuse && n >= 2 && !is_multi(p->gates[u.gates[0]].kind)) {
             int comps = 0, nparam = 0, sep = 0;
             for (int j = 0; j < n; ++j) {
                 const qsv_gate& G = p->gates[u.gates[j]];
@@ -345,7 +367,7 @@ std::vector<Unit> bwd_units(const qsv_plan_t* p, const std::vector<int>& gates, 
             const qsv_gate& G = p->gates[u.gates[j]];
             gate_sets(G, x.D, x.C);
             x.C &= ~x.D;
-            x.qubit = is_two(G.kind) ? G.q1 : G.q0;
+            x.qubit = target_of(G);
             units.push_back(x);
         }
     }
@@ -428,6 +450,11 @@ struct PassBuilder {
                     if (lb >= 0 && st.reg[i] == lb) return i;
                 return -1;
             };
+            // control encoding: register position, or kCtlNonReg | index-bit shift
+            auto ctl_code = [&](int qubit) {
+                const int pc = pos_of(qubit);
+                return pc >= 0 ? pc : (kCtlNonReg | (W - 1 - qubit));
+            };
             st.op0 = (int32_t)p->ops.size();
             int sign_op = -1;  // open OP_SIGN being extended
             for (int ui : grp.second) {
@@ -435,7 +462,7 @@ struct PassBuilder {
                 if (backward) order.insert(order.end(), U.gates.rbegin(), U.gates.rend());
                 else order.insert(order.end(), U.gates.begin(), U.gates.end());
                 const qsv_gate& G = p->gates[U.gates[0]];
-                const bool is_cz = U.gates.size() == 1 && G.kind == QSV_CZ;
+                const bool is_cz = U.gates.size() == 1 && is_zz(G.kind);
                 auto starts_timelines = [&]() {
                     if (!backward || first_on.empty()) return false;
                     const qsv_gate& G0 = p->gates[U.gates[0]];
@@ -445,39 +472,42 @@ struct PassBuilder {
                 };
                 if (is_cz && starts_timelines()) continue;
                 if (is_cz) {
+                    // CZ / CCZ: flip where every qubit is 1. Register qubits select
+                    // the flipped registers; the other qubits gate them by index bits.
                     if (sign_op < 0) {
                         DOp o;
                         std::memset(&o, 0, sizeof o);
                         o.kind = OP_SIGN;
                         o.pos = 0;  // uniform mask
-                        o.ctl = -1;
+                        o.ctl = o.ctl2 = -1;
                         o.term0 = (int32_t)p->terms.size();
                         o.nterm = 0;
                         p->ops.push_back(o);
                         sign_op = (int)p->ops.size() - 1;
                     }
                     DOp& o = p->ops[sign_op];
-                    const int pa = pos_of(G.q0), pb = pos_of(G.q1);
-                    const int sa = W - 1 - G.q0, sb = W - 1 - G.q1;
-                    if (pa >= 0 && pb >= 0) {
-                        int mask = 0;
-                        for (int r = 0; r < kRegs; ++r)
-                            if ((r >> pa & 1) && (r >> pb & 1)) mask |= 1 << r;
+                    int mask = 0xFFFF;
+                    std::vector<int> glob;
+                    for (int q = 0; q < W; ++q) {
+                        if (!(qmask(G) >> q & 1)) continue;
+                        const int pq = pos_of(q);
+                        if (pq >= 0) {
+                            int m = 0;
+                            for (int r = 0; r < kRegs; ++r)
+                                if (r >> pq & 1) m |= 1 << r;
+                            mask &= m;
+                        } else {
+                            glob.push_back(W - 1 - q);
+                        }
+                    }
+                    if (glob.empty()) {
                         o.pos ^= mask;
                     } else {
                         DTerm t;
-                        std::memset(&t, 0, sizeof t);
-                        if (pa >= 0 || pb >= 0) {
-                            const int pr = pa >= 0 ? pa : pb;
-                            t.s0 = pa >= 0 ? sb : sa;
-                            t.s1 = -1;
-                            for (int r = 0; r < kRegs; ++r)
-                                if (r >> pr & 1) t.mask |= 1 << r;
-                        } else {
-                            t.s0 = sa;
-                            t.s1 = sb;
-                            t.mask = 0xFFFF;
-                        }
+                        t.s0 = glob[0];
+                        t.s1 = glob.size() > 1 ? glob[1] : -1;
+                        t.s2 = glob.size() > 2 ? glob[2] : -1;
+                        t.mask = mask;
                         p->terms.push_back(t);
                         o.nterm++;
                     }
@@ -490,7 +520,7 @@ struct PassBuilder {
                     o.kind = kind;
                     o.pos = pos_of(U.qubit);
                     o.sh = W - 1 - U.qubit;
-                    o.ctl = -1;
+                    o.ctl = o.ctl2 = -1;
                     o.slot = nslot++;
                     p->ops.push_back(o);
                     return o.slot;
@@ -528,13 +558,15 @@ struct PassBuilder {
                     if (G.src != QSV_SRC_NONE) {
                         DOp o;
                         std::memset(&o, 0, sizeof o);
-                        o.kind = G.kind == QSV_RY ? OP_GY : G.kind == QSV_RZ ? OP_GZ : OP_GX;
+                        o.kind = (G.kind == QSV_RY || G.kind == QSV_CRY)   ? OP_GY
+                                 : (G.kind == QSV_RZ || G.kind == QSV_CRZ) ? OP_GZ
+                                                                           : OP_GX;
                         o.pos = pos_of(U.qubit);
                         o.sh = W - 1 - U.qubit;
-                        o.ctl = -1;
-                        if (G.kind == QSV_CRX) {
-                            const int pc = pos_of(G.q0);
-                            o.ctl = pc >= 0 ? pc : (kCtlNonReg | (W - 1 - G.q0));
+                        o.ctl = o.ctl2 = -1;
+                        if (is_multi(G.kind)) {
+                            o.ctl = ctl_code(G.q0);
+                            if (n_ctl(G.kind) == 2) o.ctl2 = ctl_code(G.q1);
                         }
                         o.mat = 0;
                         o.slot = nslot++;
@@ -555,11 +587,11 @@ struct PassBuilder {
                 o.mat = add_recipe(p, U.gates, backward);
                 o.pos = pos_of(U.qubit);
                 o.sh = W - 1 - U.qubit;
-                o.ctl = -1;
+                o.ctl = o.ctl2 = -1;
                 o.slot = -1;
-                if (is_two(G.kind) && U.gates.size() == 1) {
-                    const int pc = pos_of(G.q0);
-                    o.ctl = pc >= 0 ? pc : (kCtlNonReg | (W - 1 - G.q0));
+                if (is_multi(G.kind) && U.gates.size() == 1) {
+                    o.ctl = ctl_code(G.q0);
+                    if (n_ctl(G.kind) == 2) o.ctl2 = ctl_code(G.q1);
                 }
                 p->ops.push_back(o);
             }
@@ -574,13 +606,14 @@ struct PassBuilder {
 
 // Float32 operations per amplitude of one op (complex multiply = 6, add = 2).
 double op_flops(const DOp& o) {
-    const double half = o.ctl >= 0 ? 0.5 : 1.0;
+    // controlled ops touch half of the amplitudes per control
+    const double half = (o.ctl >= 0 ? 0.5 : 1.0) * (o.ctl2 >= 0 ? 0.5 : 1.0);
     switch (o.kind) {
     case OP_U2: return 14.0 * half;    // two complex products and a sum per output
     case OP_REAL: case OP_RXL: return 6.0 * half;
-    case OP_DIAG: return 6.0;
+    case OP_DIAG: return 6.0 * half;
     case OP_GX: case OP_GY: return 3.5 * half;
-    case OP_GZ: return 4.0;
+    case OP_GZ: return 4.0 * half;
     default: return 0.0;               // sign flips and swaps move data only
     }
 }
@@ -601,6 +634,7 @@ double pg_flops(const PGate& g, bool backward) {
     std::memset(&o, 0, sizeof o);
     o.kind = g.cls;
     o.ctl = g.csh >= 0 ? 0 : -1;
+    o.ctl2 = g.csh2 >= 0 ? 0 : -1;
     double f = op_flops(o) * (backward ? 2.0 : 1.0);
     if (backward && g.grad >= 0) {
         o.kind = g.grad;
@@ -616,9 +650,24 @@ void set_partial_layout(qsv_plan_t* p, int64_t nch) {
     p->pu_total = (int64_t)p->n_param * nch;
 }
 
+// Index-bit shifts of a per-gate launch: target and controls; a CZ / CCZ
+// lists its qubits as tsh, sh2 (and csh2).
+void pg_shifts(int W, const qsv_gate& G, PGate& x) {
+    const int nc = n_ctl(G.kind);
+    x.tsh = W - 1 - target_of(G);
+    x.csh = x.csh2 = x.sh2 = -1;
+    if (is_zz(G.kind)) {
+        x.sh2 = W - 1 - G.q0;
+        if (nc == 2) x.csh2 = W - 1 - G.q1;
+        return;
+    }
+    if (nc >= 1) x.csh = W - 1 - G.q0;
+    if (nc >= 2) x.csh2 = W - 1 - G.q1;
+}
+
 int pg_class(const qsv_plan_t* p, int g) {
     const int k = p->gates[g].kind;
-    if (k == QSV_CZ) return OP_SIGN;
+    if (is_zz(k)) return OP_SIGN;
     return recipe_class(p, std::vector<int>{g});
 }
 
@@ -659,13 +708,15 @@ int build_plan(qsv_plan_t* p) {
     std::vector<int> first2(W, p->n_gates);
     for (int g = p->n_gates - 1; g >= 0; --g) {
         const qsv_gate& G = p->gates[g];
-        if (is_two(G.kind)) first2[G.q0] = first2[G.q1] = g;
+        if (is_multi(G.kind))
+            for (int q = 0; q < W; ++q)
+                if (qmask(G) >> q & 1) first2[q] = g;
     }
     std::vector<char> in_prefix(p->n_gates, 0);
     std::vector<std::vector<int>> pre(W);
     for (int g = 0; g < p->n_gates; ++g) {
         const qsv_gate& G = p->gates[g];
-        if (!is_two(G.kind) && g < first2[G.q0]) {
+        if (!is_multi(G.kind) && g < first2[G.q0]) {
             in_prefix[g] = 1;
             pre[G.q0].push_back(g);
             p->prefix_gates.push_back(g);
@@ -693,9 +744,7 @@ int build_plan(qsv_plan_t* p) {
             const qsv_gate& G = p->gates[g];
             x.gate = g;
             x.cls = pg_class(p, g);
-            x.tsh = W - 1 - (is_two(G.kind) ? G.q1 : G.q0);
-            x.csh = (G.kind == QSV_CNOT || G.kind == QSV_CRX) ? W - 1 - G.q0 : -1;
-            x.sh2 = G.kind == QSV_CZ ? W - 1 - G.q0 : -1;
+            pg_shifts(W, G, x);
             x.mat = x.cls == OP_SIGN ? 0 : add_recipe(p, {g}, false);
             x.grad = -1;
             x.slot = -1;
@@ -708,13 +757,13 @@ int build_plan(qsv_plan_t* p) {
             const qsv_gate& G = p->gates[g];
             x.gate = g;
             x.cls = pg_class(p, g);
-            x.tsh = W - 1 - (is_two(G.kind) ? G.q1 : G.q0);
-            x.csh = (G.kind == QSV_CNOT || G.kind == QSV_CRX) ? W - 1 - G.q0 : -1;
-            x.sh2 = G.kind == QSV_CZ ? W - 1 - G.q0 : -1;
+            pg_shifts(W, G, x);
             x.mat = x.cls == OP_SIGN ? 0 : add_recipe(p, {g}, true);
             x.slot = p->param_ordinal[g];
-            x.grad = G.src == QSV_SRC_NONE ? -1
-                   : G.kind == QSV_RY ? OP_GY : G.kind == QSV_RZ ? OP_GZ : OP_GX;
+            x.grad = G.src == QSV_SRC_NONE                      ? -1
+                   : (G.kind == QSV_RY || G.kind == QSV_CRY) ? OP_GY
+                   : (G.kind == QSV_RZ || G.kind == QSV_CRZ) ? OP_GZ
+                                                             : OP_GX;
             p->pg_bwd.push_back(x);
             p->bwd_order.push_back(g);
         }
@@ -747,8 +796,8 @@ int build_plan(qsv_plan_t* p) {
         PassBuilder pb{p, true, std::vector<int>(W, p->n_gates)};
         for (int g = p->n_gates - 1; g >= 0; --g) {
             const qsv_gate& G = p->gates[g];
-            pb.first_on[G.q0] = g;
-            if (is_two(G.kind)) pb.first_on[G.q1] = g;
+            for (int q = 0; q < W; ++q)
+                if (qmask(G) >> q & 1) pb.first_on[q] = g;
         }
         const int n = (int)passes.size();
         for (int i = n - 1; i >= 0; --i) {

@@ -338,6 +338,46 @@ __device__ __forceinline__ void pair_apply(int cls, const M2& M, float2& x, floa
     y = v;
 }
 
+// Index bits fixed by a per-gate launch: the target bit (0) and the control
+// bits (1) of a pair update, or every qubit's bit (1) of a sign flip.
+struct PgBits {
+    int n;
+    int sh[3], val[3];  // ascending shifts
+};
+
+__device__ __forceinline__ PgBits pg_bits(const PGate& pg) {
+    PgBits r;
+    r.n = 0;
+    auto add = [&](int sh, int v) {
+        if (sh < 0) return;
+        int i = r.n++;
+        while (i > 0 && r.sh[i - 1] > sh) { r.sh[i] = r.sh[i - 1]; r.val[i] = r.val[i - 1]; --i; }
+        r.sh[i] = sh;
+        r.val[i] = v;
+    };
+    if (pg.cls == OP_SIGN) {
+        add(pg.tsh, 1);
+        add(pg.sh2, 1);
+        add(pg.csh2, 1);
+    } else {
+        add(pg.tsh, 0);
+        add(pg.csh, 1);
+        add(pg.csh2, 1);
+    }
+    return r;
+}
+
+// index of item `it` among the indices whose fixed bits take their values
+__device__ __forceinline__ int64_t pg_index(int64_t it, const PgBits& f) {
+    for (int i = 0; i < f.n; ++i) it = insert_bit(it, f.sh[i], f.val[i]);
+    return it;
+}
+
+// controls of a diagonal gate satisfied at index idx
+__device__ __forceinline__ bool pg_ctl_ok(const PGate& pg, int64_t idx) {
+    return (pg.csh < 0 || ((idx >> pg.csh) & 1)) && (pg.csh2 < 0 || ((idx >> pg.csh2) & 1));
+}
+
 __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, int W, int64_t B,
                                                   PGate pg, const float* __restrict__ mats,
                                                   int n_shared, int n_ps) {
@@ -347,34 +387,29 @@ __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, in
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
             if (it >= total) return;
+            if (!pg_ctl_ok(pg, it)) continue;
             const int b = (int)(it >> W);
             const M2 M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
             const float2 ph = ((it >> pg.tsh) & 1) ? M.m11 : M.m00;
             state[it] = cmul(ph, state[it]);
         }
     } else if (pg.cls == OP_SIGN) {
-        const int64_t total = B << (W - 2);
-        const int lo = min(pg.tsh, pg.sh2), hi = max(pg.tsh, pg.sh2);
+        const PgBits f = pg_bits(pg);
+        const int64_t total = B << (W - f.n);
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
             if (it >= total) return;
-            const int64_t idx = insert_bit(insert_bit(it, lo, 1), hi, 1);
+            const int64_t idx = pg_index(it, f);
             const float2 a = state[idx];
             state[idx] = make_float2(-a.x, -a.y);
         }
     } else {
-        const int nctl = pg.csh >= 0 ? 1 : 0;
-        const int64_t total = B << (W - 1 - nctl);
+        const PgBits f = pg_bits(pg);
+        const int64_t total = B << (W - f.n);
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
             if (it >= total) return;
-            int64_t i0;
-            if (nctl) {
-                const int lo = min(pg.tsh, pg.csh), hi = max(pg.tsh, pg.csh);
-                i0 = insert_bit(insert_bit(it, lo, lo == pg.csh), hi, hi == pg.csh);
-            } else {
-                i0 = insert_bit(it, pg.tsh, 0);
-            }
+            const int64_t i0 = pg_index(it, f);
             const int64_t i1 = i0 | (int64_t(1) << pg.tsh);
             const int b = (int)(i0 >> W);
             M2 M{};
@@ -425,6 +460,7 @@ __global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2
         const int64_t n = int64_t(1) << W, per = n / nch;
         for (int64_t e = t; e < per; e += 256) {
             const int64_t idx = chunk * per + e;
+            if (!pg_ctl_ok(pg, idx)) continue;
             const int bit = (idx >> pg.tsh) & 1;
             float2 p = P[idx], l = L[idx];
             if (pg.grad == OP_GZ) acc += bit ? -im_conj_mul(l, p) : im_conj_mul(l, p);
@@ -433,23 +469,20 @@ __global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2
             L[idx] = cmul(ph, l);
         }
     } else if (pg.cls == OP_SIGN) {
-        const int64_t n = int64_t(1) << (W - 2), per = n / nch;
-        const int lo = min(pg.tsh, pg.sh2), hi = max(pg.tsh, pg.sh2);
+        const PgBits f = pg_bits(pg);
+        const int64_t n = int64_t(1) << (W - f.n), per = n / nch;
         for (int64_t e = t; e < per; e += 256) {
-            const int64_t idx = insert_bit(insert_bit(chunk * per + e, lo, 1), hi, 1);
+            const int64_t idx = pg_index(chunk * per + e, f);
             const float2 p = P[idx], l = L[idx];
             P[idx] = make_float2(-p.x, -p.y);
             L[idx] = make_float2(-l.x, -l.y);
         }
     } else {
-        const int nctl = pg.csh >= 0 ? 1 : 0;
-        const int64_t n = int64_t(1) << (W - 1 - nctl), per = n / nch;
-        const int lo = nctl ? min(pg.tsh, pg.csh) : pg.tsh;
-        const int hi = nctl ? max(pg.tsh, pg.csh) : pg.tsh;
+        const PgBits f = pg_bits(pg);
+        const int64_t n = int64_t(1) << (W - f.n), per = n / nch;
         for (int64_t e = t; e < per; e += 256) {
             const int64_t it = chunk * per + e;
-            const int64_t i0 = nctl ? insert_bit(insert_bit(it, lo, lo == pg.csh), hi, hi == pg.csh)
-                                    : insert_bit(it, pg.tsh, 0);
+            const int64_t i0 = pg_index(it, f);
             const int64_t i1 = i0 | (int64_t(1) << pg.tsh);
             float2 p0 = P[i0], p1 = P[i1], l0 = L[i0], l1 = L[i1];
             if (pg.grad == OP_GX) acc += im_conj_mul(l0, p1) + im_conj_mul(l1, p0);
@@ -611,15 +644,22 @@ __device__ __forceinline__ void r_swap(float2 (&a)[kRegs], int cm) {
     }
 }
 
+// diagonal ops apply to the registers in cm (the controls' mask; 0xFFFF = all)
 template <int P>
-__device__ __forceinline__ void r_diag(float2 (&a)[kRegs], const M2& M) {
+__device__ __forceinline__ void r_diag(float2 (&a)[kRegs], const M2& M, int cm) {
 #pragma unroll
-    for (int k = 0; k < kRegs; ++k) a[k] = cmul((k & (1 << P)) ? M.m11 : M.m00, a[k]);
+    for (int k = 0; k < kRegs; ++k) {
+        const float2 u = cmul((k & (1 << P)) ? M.m11 : M.m00, a[k]);
+        a[k] = ((cm >> k) & 1) ? u : a[k];
+    }
 }
 
-__device__ __forceinline__ void r_phase_all(float2 (&a)[kRegs], float2 ph) {
+__device__ __forceinline__ void r_phase_all(float2 (&a)[kRegs], float2 ph, int cm) {
 #pragma unroll
-    for (int k = 0; k < kRegs; ++k) a[k] = cmul(ph, a[k]);
+    for (int k = 0; k < kRegs; ++k) {
+        const float2 u = cmul(ph, a[k]);
+        a[k] = ((cm >> k) & 1) ? u : a[k];
+    }
 }
 
 __device__ __forceinline__ void r_flip(float2 (&a)[kRegs], int flip) {
@@ -644,30 +684,31 @@ __device__ __forceinline__ float r_gx(const float2 (&ps)[kRegs], const float2 (&
     return acc;
 }
 template <int P>
-__device__ __forceinline__ float r_gy(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs]) {
+__device__ __forceinline__ float r_gy(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs], int cm) {
     float acc = 0.f;
 #pragma unroll
     for (int k = 0; k < kRegs; ++k) {
         if (k & (1 << P)) continue;
         const int k1 = k | (1 << P);
-        acc += re_conj_mul(lm[k1], ps[k]) - re_conj_mul(lm[k], ps[k1]);
+        const float v = re_conj_mul(lm[k1], ps[k]) - re_conj_mul(lm[k], ps[k1]);
+        acc += ((cm >> k) & 1) ? v : 0.f;
     }
     return acc;
 }
 template <int P>
-__device__ __forceinline__ float r_gz(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs]) {
+__device__ __forceinline__ float r_gz(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs], int cm) {
     float acc = 0.f;
 #pragma unroll
     for (int k = 0; k < kRegs; ++k) {
         const float v = im_conj_mul(lm[k], ps[k]);
-        acc += (k & (1 << P)) ? -v : v;
+        acc += ((cm >> k) & 1) ? ((k & (1 << P)) ? -v : v) : 0.f;
     }
     return acc;
 }
-__device__ __forceinline__ float r_gz_all(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs]) {
+__device__ __forceinline__ float r_gz_all(const float2 (&ps)[kRegs], const float2 (&lm)[kRegs], int cm) {
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < kRegs; ++k) acc += im_conj_mul(lm[k], ps[k]);
+    for (int k = 0; k < kRegs; ++k) acc += ((cm >> k) & 1) ? im_conj_mul(lm[k], ps[k]) : 0.f;
     return acc;
 }
 
@@ -695,7 +736,7 @@ __device__ __forceinline__ int ctl_mask(int ctl, int gT) {
 __device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], const M2& M, int gT,
                                          const DTerm* __restrict__ terms) {
     const bool ctl = op.ctl >= 0;
-    const int cm = ctl_mask(op.ctl, gT);
+    const int cm = ctl_mask(op.ctl, gT) & ctl_mask(op.ctl2, gT);
     switch (op.kind) {
     case OP_U2:
 #define C_(P) if (ctl) r_u2<P, true>(a, M, cm); else r_u2<P, false>(a, M, cm)
@@ -719,22 +760,20 @@ __device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], cons
         break;
     case OP_DIAG:
         if (op.pos >= 0) {
-#define C_(P) r_diag<P>(a, M)
+#define C_(P) r_diag<P>(a, M, cm)
             QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
         } else {
-            r_phase_all(a, ((gT >> op.sh) & 1) ? M.m11 : M.m00);
+            r_phase_all(a, ((gT >> op.sh) & 1) ? M.m11 : M.m00, cm);
         }
         break;
     case OP_SIGN: {
         int flip = op.pos;
         for (int i = 0; i < op.nterm; ++i) {
             const DTerm tm = terms[op.term0 + i];
-            if (tm.s1 < 0) {
-                if ((gT >> tm.s0) & 1) flip ^= tm.mask;
-            } else if ((gT >> tm.s0) & (gT >> tm.s1) & 1) {
-                flip ^= 0xFFFF;
-            }
+            const bool on = ((gT >> tm.s0) & 1) && (tm.s1 < 0 || ((gT >> tm.s1) & 1)) &&
+                            (tm.s2 < 0 || ((gT >> tm.s2) & 1));
+            if (on) flip ^= tm.mask;
         }
         r_flip(a, flip);
         break;
@@ -746,23 +785,23 @@ __device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], cons
 __device__ __forceinline__ float grad_op(const DOp& op, const float2 (&ps)[kRegs],
                                          const float2 (&lm)[kRegs], int gT) {
     float v = 0.f;
+    const bool ctl = op.ctl >= 0;
+    const int cm = ctl_mask(op.ctl, gT) & ctl_mask(op.ctl2, gT);
     if (op.kind == OP_GX) {
-        const bool ctl = op.ctl >= 0;
-        const int cm = ctl_mask(op.ctl, gT);
 #define C_(P) v = ctl ? r_gx<P, true>(ps, lm, cm) : r_gx<P, false>(ps, lm, cm)
         QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
     } else if (op.kind == OP_GY) {
-#define C_(P) v = r_gy<P>(ps, lm)
+#define C_(P) v = r_gy<P>(ps, lm, cm)
         QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
     } else {
         if (op.pos >= 0) {
-#define C_(P) v = r_gz<P>(ps, lm)
+#define C_(P) v = r_gz<P>(ps, lm, cm)
             QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
         } else {
-            v = r_gz_all(ps, lm);
+            v = r_gz_all(ps, lm, cm);
             if ((gT >> op.sh) & 1) v = -v;
         }
     }
@@ -1453,6 +1492,19 @@ size_t multi_lds(const qsv_plan_t* p) {
 
 
 
+// Per-gate launches: index bits fixed per item (target + controls, or the
+// qubits of a sign flip) and the fraction of the amplitudes a gate changes.
+int pg_fixed_bits(const PGate& g) {
+    const int nctl = (g.csh >= 0) + (g.csh2 >= 0);
+    return g.cls == OP_SIGN ? 2 + (g.csh2 >= 0) : 1 + nctl;
+}
+
+double pg_touched(const PGate& g) {
+    const int nctl = (g.csh >= 0) + (g.csh2 >= 0);
+    if (g.cls == OP_SIGN) return 1.0 / (double)(1 << pg_fixed_bits(g));
+    return 1.0 / (double)(1 << nctl);
+}
+
 size_t pass_lds_fwd(const qsv_plan_t* p) {
     const int m = std::min(p->opts.tile_qubits, p->W);
     return (size_t(1) << m) * 8;
@@ -1526,18 +1578,28 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
-        if (G.kind < QSV_H || G.kind > QSV_CRX) {
+        if (G.kind < QSV_H || G.kind > QSV_CCRX) {
             std::snprintf(buf, sizeof buf, "gate %d: unknown kind %d", g, G.kind);
             set_error(buf);
             return QSV_ERR_GATE;
         }
-        const bool two = G.kind == QSV_CNOT || G.kind == QSV_CZ || G.kind == QSV_CRX;
-        if (G.q0 < 0 || G.q0 >= n_qubits || (two && (G.q1 < 0 || G.q1 >= n_qubits || G.q1 == G.q0))) {
-            std::snprintf(buf, sizeof buf, "gate %d: qubits (%d, %d) invalid for W = %d", g, G.q0, G.q1, n_qubits);
+        const int nq = 1 + (G.kind == QSV_CNOT || G.kind == QSV_CZ || G.kind == QSV_CRX ||
+                            G.kind == QSV_CRY || G.kind == QSV_CRZ)
+                     + 2 * (G.kind == QSV_CCX || G.kind == QSV_CCZ || G.kind == QSV_CCRX);
+        const int qs[3] = {G.q0, G.q1, G.q2};
+        bool ok = true;
+        for (int i = 0; i < nq; ++i) {
+            ok &= qs[i] >= 0 && qs[i] < n_qubits;
+            for (int j = 0; j < i; ++j) ok &= qs[i] != qs[j];
+        }
+        if (!ok) {
+            std::snprintf(buf, sizeof buf, "gate %d: qubits (%d, %d, %d) invalid for W = %d", g, G.q0, G.q1,
+                          G.q2, n_qubits);
             set_error(buf);
             return QSV_ERR_QUBIT;
         }
-        const bool param = G.kind == QSV_RX || G.kind == QSV_RY || G.kind == QSV_RZ || G.kind == QSV_CRX;
+        const bool param = G.kind == QSV_RX || G.kind == QSV_RY || G.kind == QSV_RZ || G.kind == QSV_CRX ||
+                           G.kind == QSV_CRY || G.kind == QSV_CRZ || G.kind == QSV_CCRX;
         const bool ok_src = param ? (G.src == QSV_SRC_WEIGHT || G.src == QSV_SRC_INPUT) : G.src == QSV_SRC_NONE;
         const bool ok_idx = G.src == QSV_SRC_WEIGHT ? (G.idx >= 0 && G.idx < n_weights)
                           : G.src == QSV_SRC_INPUT ? (G.idx >= 0 && G.idx < n_inputs) : true;
@@ -1704,10 +1766,10 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
         for (size_t i = 0; i < p->pg_fwd.size(); ++i) {
             const PGate& pg = p->pg_fwd[i];
             int64_t items;
-            double touched;  // fraction of the amplitudes the gate changes
-            if (pg.cls == OP_DIAG) { items = B << W; touched = 1.0; }
-            else if (pg.cls == OP_SIGN) { items = B << (W - 2); touched = 0.25; }
-            else { items = B << (W - 1 - (pg.csh >= 0 ? 1 : 0)); touched = pg.csh >= 0 ? 0.5 : 1.0; }
+            const double touched = pg_touched(pg);  // fraction of the amplitudes the gate changes
+            const int nfix = pg_fixed_bits(pg);
+            if (pg.cls == OP_DIAG) items = B << W;
+            else items = B << (W - nfix);
             const int64_t blocks = (items + 256 * kPgItems - 1) / (256 * kPgItems);
             hipEvent_t ev = prof_begin(p, s);
             hipLaunchKernelGGL(k_pg_apply, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
@@ -1841,7 +1903,7 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
         prof_end(p, s, ev, K_ADJ_INIT, 24.0 * amps, 2.0 * W * amps);
         for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
             const PGate& pg = p->pg_bwd[i];
-            const double touched = pg.cls == OP_SIGN ? 0.25 : (pg.csh >= 0 ? 0.5 : 1.0);
+            const double touched = pg_touched(pg);
             ev = prof_begin(p, s);
             hipLaunchKernelGGL(k_pg_adj, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi,
                                lam, W, (int)B, pg, (const float*)mats, p->n_shared_mats,
@@ -2076,12 +2138,12 @@ int qsv_plan_estimate(const qsv_plan_t* p, int64_t B, double hbm_gbs, double alu
             t += sweep(24.0 * a, 0.0);  // adjoint init
             for (size_t i = 0; i < p->pg_fwd.size(); ++i) {
                 const PGate& g = p->pg_fwd[i];
-                const double touched = g.cls == OP_SIGN ? 0.25 : (g.cls != OP_DIAG && g.csh >= 0 ? 0.5 : 1.0);
+                const double touched = pg_touched(g);
                 t += sweep(16.0 * touched * a, p->pg_fwd_flops[i] * a);
             }
             for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
                 const PGate& g = p->pg_bwd[i];
-                const double touched = g.cls == OP_SIGN ? 0.25 : (g.csh >= 0 ? 0.5 : 1.0);
+                const double touched = pg_touched(g);
                 t += sweep(32.0 * touched * a, p->pg_bwd_flops[i] * a);
             }
             launches += (int64_t)(p->pg_fwd.size() + p->pg_bwd.size()) + 2;

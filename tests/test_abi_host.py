@@ -46,7 +46,7 @@ def _plan_rc(W, gates, n_w=4, n_in=2, opts=None):
 
 
 @pytest.mark.parametrize("W,gate,code", [
-    (3, (11, 0, -1, 0, -1), -3),          # unknown kind
+    (3, (99, 0, -1, 0, -1), -3),          # unknown kind
     (3, (-1, 0, -1, 0, -1), -3),
     (3, (0, 3, -1, 0, -1), -2),           # qubit >= W
     (3, (0, -1, -1, 0, -1), -2),
@@ -57,6 +57,13 @@ def _plan_rc(W, gates, n_w=4, n_in=2, opts=None):
     (3, (4, 0, -1, 0, -1), -4),           # rotation without an angle source
     (3, (0, 0, -1, 1, 0), -4),            # fixed gate with an angle source
     (31, (0, 0, -1, 0, -1), -5),          # W above the limit
+    (3, (12, 0, 1, 0, -1, 1), -2),        # CCX with a repeated qubit
+    (3, (12, 0, 1, 0, -1, -1), -2),       # CCX without a target
+    (3, (13, 0, 1, 0, -1, 3), -2),        # CCZ target out of range
+    (3, (10, 2, 2, 1, 0), -2),            # CRY on one qubit
+    (3, (14, 0, 1, 0, -1, 2), -4),        # CCRX without an angle source
+    (3, (12, 0, 1, 1, 0, 2), -4),         # CCX with an angle source
+    (3, (15, 0, -1, 0, -1), -3),          # unknown kind
     (0, (0, 0, -1, 0, -1), -1),
 ])
 def test_plan_rejects(lib, W, gate, code):

@@ -214,3 +214,42 @@ def test_weight_remap(orc, method):
     assert ok, ("weights", rel)
     ok, rel = grad_close(got["gx"].cpu().numpy(), gx)
     assert ok, ("inputs", rel)
+
+
+# -- multi-qubit gates: CRY, CRZ, Toffoli (CCX), CCZ, CCRX ----------------------
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("W,ng,seed", [(3, 60, 71), (6, 120, 72), (9, 150, 73), (13, 150, 74)])
+def test_controlled_kinds(orc, method, W, ng, seed):
+    rng = np.random.default_rng(seed)
+    c = I.random_mixed(W, ng, rng, n_inputs=3, p_input=0.3, kinds=I.ALL_KINDS)
+    _check(c, 3, seed, orc, method)
+
+
+@pytest.mark.parametrize("method", ["fused", "fused_tables"])
+@pytest.mark.parametrize("W,m,cq", [(9, 4, 1), (11, 6, 2), (13, 8, 3)])
+def test_controlled_kinds_small_tiles(orc, method, W, m, cq):
+    """Small tiles put controls and targets outside the registers and the tile."""
+    rng = np.random.default_rng(100 + W)
+    c = I.random_mixed(W, 120, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS)
+    _check(c, 2, 100 + W, orc, method, tile_qubits=m, low_qubits=cq)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_toffoli_truth_table(method):
+    W = 5
+    for order in [(0, 1, 2), (4, 0, 3), (2, 4, 0)]:
+        c0, c1, t = order
+        for bits in range(32):
+            circ = I.Circuit(W, name="toffoli")
+            for q in range(W):
+                if (bits >> (W - 1 - q)) & 1:
+                    circ.fixed("X", q)
+            circ.fixed("CCX", c0, c1, t)
+            got = gpu_run(circ, np.zeros(0, np.float32), np.zeros((1, 0), np.float32), 1, **_opts(method))
+            st = got["state"].cpu().numpy()[0]
+            b = [(bits >> (W - 1 - q)) & 1 for q in range(W)]
+            if b[c0] and b[c1]:
+                b[t] ^= 1
+            want = sum(v << (W - 1 - q) for q, v in enumerate(b))
+            assert st[want] == 1 and np.count_nonzero(st) == 1, (order, bits)

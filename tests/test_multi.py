@@ -122,6 +122,13 @@ def test_multi_small_mixed(orc):
 
 
 @pytest.mark.gpu
+def test_multi_controlled_kinds(orc):
+    rng = np.random.default_rng(13)
+    cs = [I.random_mixed(int(n), 80, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS) for n in (4, 7, 10, 12)]
+    _run_multi(cs, 2, 13, orc)
+
+
+@pytest.mark.gpu
 def test_multi_weight_remap(orc):
     _run_multi(_mixed_set(12, 5, 4, 11), 2, 12, orc, weight_remap=1)
 
