@@ -158,7 +158,8 @@ def bench_uneven(args, torch, dev, binding, inputs):
 
     from paper_2404_09213_amd import tune
     cs = inputs.uneven_set(512, seed=1004)
-    space = {"fuse_width": [1, 2, 3], "tile_qubits": [10, 11, 12], "low_qubits": [3, 4, 5]}
+    space = {"fuse_width": [1, 2, 3], "tile_qubits": [10, 11, 12], "low_qubits": [3, 4, 5],
+             "splitter": [0, 1]}
     tr = tune.tune(cs, 1, multi=True, space=space, top=3, steps=3, log=lambda m: log(args, m))
     t_plan = time.perf_counter()
     plan = binding.MultiPlan(cs, **tr["opts"])

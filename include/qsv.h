@@ -131,7 +131,11 @@ typedef struct {
                             (quantum weight remapping, section "Additional
                             Optimizations": weights mapped into (-pi, pi) by tanh);
                             weight gradients are then with respect to w. 0 (default): off */
-    int32_t reserved[3];
+    int32_t splitter;    /* 0 (default): greedy split in program order (section
+                            "Circuit Splitting"); 1: list scheduling over the
+                            dependency graph (the graph-based split named as future
+                            work in section "Conclusion") */
+    int32_t reserved[2];
 } qsv_opts;
 
 typedef struct {

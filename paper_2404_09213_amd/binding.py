@@ -46,7 +46,8 @@ class qsv_opts(ctypes.Structure):
                 ("tile_qubits", ctypes.c_int32), ("low_qubits", ctypes.c_int32),
                 ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
                 ("bwd_gate_by_gate", ctypes.c_int32), ("mfma", ctypes.c_int32),
-                ("weight_remap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("weight_remap", ctypes.c_int32), ("splitter", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -314,8 +315,10 @@ def qsv_last_error():
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
               max_pass_grads=None, codegen=None, bwd_gate_by_gate=None, mfma=None,
-              weight_remap=None):
+              weight_remap=None, splitter=None):
     o = qsv_default_opts()
+    if splitter is not None:
+        o.splitter = int(splitter)
     if weight_remap is not None:
         o.weight_remap = int(weight_remap)
     if mfma is not None:

@@ -159,6 +159,74 @@ std::vector<Block> split(const qsv_plan_t* p, const std::vector<int>& seq, int k
     return blocks;
 }
 
+// Dependency-graph splitter (the graph-based split proposed as future work in
+// section "Conclusion"): list scheduling over the circuit's dependency DAG
+// (an edge joins consecutive gates on a qubit). A block is filled from the
+// gates whose predecessors are all placed, each time taking the ready gate
+// that adds the fewest new qubits, then the one with the longest chain of
+// dependants behind it, then the earliest; a block closes when no ready gate
+// fits within k qubits. Unlike the program-order rule it may place a gate
+// before gates it commutes with trivially (disjoint qubits), so it can fill a
+// block with gates the program lists far apart.
+std::vector<Block> split_dag(const qsv_plan_t* p, const std::vector<int>& seq, int k) {
+    const int n = (int)seq.size();
+    std::vector<std::vector<int>> succ(n);
+    std::vector<int> npred(n, 0), last(p->W, -1);
+    std::vector<uint32_t> qm(n);
+    for (int i = 0; i < n; ++i) {
+        qm[i] = qmask(p->gates[seq[i]]);
+        std::vector<int> preds;
+        for (int b = 0; b < p->W; ++b)
+            if (qm[i] >> b & 1) {
+                if (last[b] >= 0 && std::find(preds.begin(), preds.end(), last[b]) == preds.end())
+                    preds.push_back(last[b]);
+                last[b] = i;
+            }
+        for (int j : preds) succ[j].push_back(i);
+        npred[i] = (int)preds.size();
+    }
+    std::vector<int> height(n, 0);  // longest chain of dependants
+    for (int i = n - 1; i >= 0; --i)
+        for (int j : succ[i]) height[i] = std::max(height[i], height[j] + 1);
+    std::vector<int> ready;
+    for (int i = 0; i < n; ++i)
+        if (npred[i] == 0) ready.push_back(i);
+    std::vector<Block> blocks;
+    int placed = 0;
+    while (placed < n) {
+        Block blk;
+        uint32_t Q = 0;
+        for (;;) {
+            int best = -1, bgrow = 0;
+            for (int r : ready) {
+                const uint32_t nq = Q | qm[r];
+                if (Q && popc(nq) > k) continue;
+                const int grow = popc(nq) - popc(Q);
+                if (best < 0 || grow < bgrow || (grow == bgrow && (height[r] > height[best] ||
+                                                                   (height[r] == height[best] && r < best)))) {
+                    best = r;
+                    bgrow = grow;
+                }
+            }
+            if (best < 0) break;
+            ready.erase(std::find(ready.begin(), ready.end(), best));
+            blk.gates.push_back(seq[best]);
+            Q |= qm[best];
+            ++placed;
+            for (int s2 : succ[best])
+                if (--npred[s2] == 0) ready.push_back(s2);
+            if (popc(Q) > k) break;  // a gate wider than k stays alone
+        }
+        blk.Q = Q;
+        blocks.push_back(blk);
+    }
+    return blocks;
+}
+
+std::vector<Block> split_with(const qsv_plan_t* p, const std::vector<int>& seq, int k) {
+    return p->opts.splitter == 1 ? split_dag(p, seq, k) : split(p, seq, k);
+}
+
 struct BlockSets { uint32_t D = 0, C = 0; int nparam = 0; };
 
 BlockSets block_sets(const qsv_plan_t* p, const Block& b) {
@@ -732,7 +800,7 @@ int build_plan(qsv_plan_t* p) {
     p->fwd_order = p->prefix_gates;
 
     // splitter over the whole list (reported; drives the backward schedule)
-    p->blocks = split(p, all, o.fuse_width);
+    p->blocks = split_with(p, all, o.fuse_width);
     p->block_of_gate.assign(p->n_gates, -1);
     for (size_t b = 0; b < p->blocks.size(); ++b)
         for (int g : p->blocks[b].gates) p->block_of_gate[g] = (int32_t)b;
@@ -785,7 +853,7 @@ int build_plan(qsv_plan_t* p) {
     max_grads = std::max(max_grads, 1);
     {
         std::vector<uint32_t> dense;
-        auto passes = pack_passes(p, split(p, body, o.fuse_width), m, c, 1 << 30, dense);
+        auto passes = pack_passes(p, split_with(p, body, o.fuse_width), m, c, 1 << 30, dense);
         PassBuilder pb{p, false, {}};
         for (size_t i = 0; i < passes.size(); ++i)
             pb.build(passes[i], dense[i], m, c, 0, p->fwd_pass, p->fwd_order);

@@ -1575,6 +1575,7 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
@@ -1967,6 +1968,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.bwd_gate_by_gate != 0 && o.bwd_gate_by_gate != 1) { set_error("bwd_gate_by_gate must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
     std::vector<CircuitIn> cs;
     int64_t row = 0;
     for (int c = 0; c < n_circuits; ++c) {

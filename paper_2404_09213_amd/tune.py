@@ -1,4 +1,4 @@
-"""Choice of fusion width k, tile qubits m and low qubits c for a circuit.
+"""Choice of fusion width k, tile qubits m, low qubits c and splitter for a circuit.
 
 Section "Circuit Splitting" leaves the block size to the user (it suggests
 small widths) and notes that the split is made once, when the circuit is
@@ -37,7 +37,8 @@ def default_space(circuits, multi):
     wmax = max(c.n_qubits for c in circuits)
     mmax = 12 if multi else 14
     tiles = [m for m in range(8, mmax + 1) if m <= max(wmax, 8)]
-    return {"fuse_width": [1, 2, 3, 4, 5, 6], "tile_qubits": tiles, "low_qubits": [3, 4, 5, 6]}
+    return {"fuse_width": [1, 2, 3, 4, 5, 6], "tile_qubits": tiles, "low_qubits": [3, 4, 5, 6],
+            "splitter": [0, 1]}
 
 
 def _make(circuits, multi, opts):
@@ -109,7 +110,8 @@ def tune(circuits, batch, *, multi=None, space=None, top=4, steps=3, cache=None,
         info = plan.info()
         # options that lead to the same schedule (tile clamped to the width, ...)
         sig = (info["fuse_width"], info["tile_qubits"], info["low_qubits"], info["n_fwd_passes"],
-               info["n_bwd_passes"], info["n_fwd_stages"], info["n_bwd_stages"])
+               info["n_bwd_passes"], info["n_fwd_stages"], info["n_bwd_stages"], info["n_blocks"],
+               opts.get("splitter", 0))
         if sig in seen:
             continue
         seen.add(sig)

@@ -124,21 +124,27 @@ def test_workspace_sizes_grow_with_batch(lib):
 # -- planner invariants ----------------------------------------------------------------
 
 def _qubits(g):
-    return {g[1]} | ({g[2]} if g[0] in ("CNOT", "CZ", "CRX") else set())
+    q = {g[1]}
+    if g[0] in I.TWO_QUBIT or g[0] in I.THREE_QUBIT:
+        q.add(g[2])
+    if g[0] in I.THREE_QUBIT:
+        q.add(g[5])
+    return q
 
 
 def _circuits():
     rng = np.random.default_rng(5)
     out = [I.rx_ry_rz_cz_ladder(12, 3), I.ry_rz_cnot_ring(9, 3), I.random_layers(10, 6, rng),
            I.random_mixed(8, 150, rng, n_inputs=3, p_input=0.2), I.random_mixed(3, 60, rng),
-           I.random_mixed(6, 80, rng)]
+           I.random_mixed(6, 80, rng), I.random_mixed(7, 90, rng, kinds=I.ALL_KINDS)]
     return out
 
 
+@pytest.mark.parametrize("splitter", [0, 1])
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 6])
-def test_splitter_invariants(lib, k):
+def test_splitter_invariants(lib, k, splitter):
     for c in _circuits():
-        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, fuse_width=k)
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, fuse_width=k, splitter=splitter)
         blk = p.gate_blocks()
         assert np.all(blk >= 0)
         nb = blk.max() + 1
@@ -162,13 +168,31 @@ def test_splitter_block_counts_ladder(lib):
     assert counts == [68, 48, 40]
 
 
+def test_dag_splitter_needs_no_more_blocks(lib):
+    """The dependency-graph splitter against the program-order rule: the
+    20-qubit ladder at k = 4, 5, 6 and random-layer circuits at k = 4."""
+    c = I.rx_ry_rz_cz_ladder(20, 10)
+    counts = [B.Plan(20, c.gates, c.n_weights, c.n_inputs, fuse_width=k, splitter=1).info()["n_blocks"]
+              for k in (4, 5, 6)]
+    assert counts == [66, 48, 35]
+    rng = np.random.default_rng(7)
+    tot = [0, 0]
+    for _ in range(30):
+        c = I.random_layers(int(rng.integers(8, 19)), int(rng.integers(2, 13)), rng)
+        for sp in (0, 1):
+            tot[sp] += B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, fuse_width=4,
+                              splitter=sp).info()["n_blocks"]
+    assert tot == [501, 420]
+
+
+@pytest.mark.parametrize("splitter", [0, 1])
 @pytest.mark.parametrize("method", ["fused", "per_gate"])
 @pytest.mark.parametrize("k,m,cq", [(5, 12, 5), (3, 8, 2), (2, 6, 0), (6, 10, 4), (4, 4, 1)])
-def test_schedule_orders_are_valid(orc, lib, method, k, m, cq):
+def test_schedule_orders_are_valid(orc, lib, method, k, m, cq, splitter):
     # Applying the gates in the order the kernels use must give the same state.
     for c in _circuits():
         p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method=method, fuse_width=k,
-                   tile_qubits=m, low_qubits=cq)
+                   tile_qubits=m, low_qubits=cq, splitter=splitter)
         w, x = I.draw_angles(c, 2, 3)
         ref = orc.forward(c.n_qubits, c.gates, w.astype(np.float64), x.astype(np.float64), 2)
         for which in (0, 1):

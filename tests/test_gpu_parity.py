@@ -253,3 +253,14 @@ def test_toffoli_truth_table(method):
                 b[t] ^= 1
             want = sum(v << (W - 1 - q) for q, v in enumerate(b))
             assert st[want] == 1 and np.count_nonzero(st) == 1, (order, bits)
+
+
+@pytest.mark.parametrize("method", ["fused", "fused_tables"])
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_dag_splitter(orc, method, k):
+    """Plans split by the dependency-graph list scheduler (splitter = 1)."""
+    rng = np.random.default_rng(200 + k)
+    for c in (I.random_layers(12, 6, rng),
+              I.random_mixed(10, 150, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS),
+              I.rx_ry_rz_cz_ladder(14, 3)):
+        _check(c, 2, 200 + k, orc, method, fuse_width=k, splitter=1)
