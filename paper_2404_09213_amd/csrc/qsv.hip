@@ -820,6 +820,15 @@ __device__ __forceinline__ int tile_base_of(const DPass* __restrict__ P, int tbi
 
 // One fused forward pass over one tile of one sample. st: the sample's 2^W
 // amplitudes; tis: tile index within the sample; lds: 2^m float2.
+// An op's 2x2 matrix (ops without one get zeros).
+__device__ __forceinline__ M2 op_matrix(const DOp& op, const float* __restrict__ mats, int b, int n_shared,
+                                        int n_ps) {
+    M2 M{};
+    if (op.kind != OP_SIGN && op.kind != OP_SWAP && op.kind < OP_GX)
+        M = load_m2(mat_ptr(mats, op.mat, b, n_shared, n_ps));
+    return M;
+}
+
 __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
                                               const DStage* __restrict__ S,
                                               const DOp* __restrict__ O,
@@ -830,6 +839,7 @@ __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
     const int m = P->m;
     const int t = threadIdx.x;
     const bool act = t < (1 << (m - kRegBits));
+    const bool wave_on = (t >> 6) < (((1 << (m - kRegBits)) + 63) >> 6);
     const int base = tile_base_of(P, W - m, tis);
 
     int cur[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
@@ -849,11 +859,23 @@ __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
             if (act) lds_load(lds, L, a);
             __syncthreads();
         }
-        for (int oi = stg.op0; oi < stg.op1; ++oi) {
-            const DOp op = O[oi];
-            M2 M{};
-            if (op.kind != OP_SIGN && op.kind != OP_SWAP) M = load_m2(mat_ptr(mats, op.mat, b, n_shared, n_ps));
-            apply_op(op, a, M, L.gT, Tm);
+        // waves without an active lane only keep the barrier count (wave-uniform
+        // branch). The next op and its matrix are fetched while the current one
+        // is applied, so their load latency overlaps the arithmetic.
+        if (wave_on && stg.op0 < stg.op1) {
+            DOp op = O[stg.op0];
+            M2 M = op_matrix(op, mats, b, n_shared, n_ps);
+            for (int oi = stg.op0; oi < stg.op1; ++oi) {
+                DOp nop = op;
+                M2 nM = M;
+                if (oi + 1 < stg.op1) {
+                    nop = O[oi + 1];
+                    nM = op_matrix(nop, mats, b, n_shared, n_ps);
+                }
+                apply_op(op, a, M, L.gT, Tm);
+                op = nop;
+                M = nM;
+            }
         }
     }
     const int nat[kRegBits] = {m - 4, m - 3, m - 2, m - 1};
@@ -911,9 +933,12 @@ __device__ __forceinline__ void pass_bwd_tile(
     const int nthr = 1 << (m - kRegBits);
     const bool act = t < nthr;
     const int nwaves = (int)(blockDim.x >> 6);
+    const int waves_on = (nthr + 63) >> 6;  // waves holding at least one active lane
+    const bool wave_on = (t >> 6) < waves_on;
     // float32 partials per 16-lane row and component slot, then float64 sums
     const int ng = P->n_gslots;
     const int nrows = nwaves * 4;
+    const int nrows_on = waves_on * 4;
     float* red = reinterpret_cast<float*>(lds + (1 << m));
     double* csum = reinterpret_cast<double*>(lds + (1 << m) + ((nrows * ng + 1) >> 1));
     const int tbits = W - m;
@@ -966,16 +991,28 @@ __device__ __forceinline__ void pass_bwd_tile(
             __syncthreads();
             L = Ln;
         }
-        for (int oi = stg.op0; oi < stg.op1; ++oi) {
-            const DOp op = O[oi];
-            if (op.kind >= OP_GX) {
-                // every lane of a row stores the row's sum (same value, same address)
-                red[(wave * 4 + (lane >> 4)) * ng + op.slot] = row_sum(grad_op(op, ps, lm, L.gT));
-            } else {
-                M2 M{};
-                if (op.kind != OP_SIGN && op.kind != OP_SWAP) M = load_m2(mat_ptr(mats, op.mat, b, n_shared, n_ps));
-                apply_op(op, ps, M, L.gT, Tm);
-                apply_op(op, lm, M, L.gT, Tm);
+        // waves without an active lane only keep the barrier count (wave-uniform
+        // branch); their rows are left out of the sums below
+        if (wave_on && stg.op0 < stg.op1) {
+            // next op and matrix fetched while the current one is applied
+            DOp op = O[stg.op0];
+            M2 M = op_matrix(op, mats, b, n_shared, n_ps);
+            for (int oi = stg.op0; oi < stg.op1; ++oi) {
+                DOp nop = op;
+                M2 nM = M;
+                if (oi + 1 < stg.op1) {
+                    nop = O[oi + 1];
+                    nM = op_matrix(nop, mats, b, n_shared, n_ps);
+                }
+                if (op.kind >= OP_GX) {
+                    // every lane of a row stores the row's sum (same value, same address)
+                    red[(wave * 4 + (lane >> 4)) * ng + op.slot] = row_sum(grad_op(op, ps, lm, L.gT));
+                } else {
+                    apply_op(op, ps, M, L.gT, Tm);
+                    apply_op(op, lm, M, L.gT, Tm);
+                }
+                op = nop;
+                M = nM;
             }
         }
     }
@@ -1002,7 +1039,7 @@ __device__ __forceinline__ void pass_bwd_tile(
     const int64_t nch = int64_t(1) << tbits;
     for (int j = t; j < ng; j += blockDim.x) {
         double s = 0.0;
-        for (int r = 0; r < nrows; ++r) s += (double)red[r * ng + j];
+        for (int r = 0; r < nrows_on; ++r) s += (double)red[r * ng + j];
         csum[j] = s;
     }
     __syncthreads();
