@@ -532,7 +532,41 @@ private:
             return s;
         };
         const int flags = ps_->flags;
-        if (!bwd_) {
+        if (!bwd_ && (flags & PF_INIT_FWD)) {
+            // The first pass generates the product state of the leading 1-qubit
+            // gates instead of loading it: amplitude idx is the product over
+            // qubits q of column 0 of q's prefix matrix, entry bit_q(idx).
+            o_ << "  f2* st = state + off;\n  {\n    f2 P_ = make_float2(1.f, 0.f);\n";
+            auto vq = [&](int q) {
+                const int slot = p_->prefix_mat[q];
+                return slot >= 0 ? "mats + " + I(8LL * slot) : "mp + " + I(8LL * (-slot - 1));
+            };
+            std::vector<int> reg_shift(kRegBits);
+            for (int r = 0; r < kRegBits; ++r) reg_shift[r] = lq(cur.reg[r]);
+            for (int q = 0; q < W_; ++q) {
+                const int sh = W_ - 1 - q;
+                if (std::find(reg_shift.begin(), reg_shift.end(), sh) != reg_shift.end()) continue;
+                o_ << "    { const float* v_ = " << vq(q) << "; const int bt_ = (gT >> " << sh << ") & 1;\n"
+                   << "      const f2 u_ = bt_ ? make_float2(v_[4], v_[5]) : make_float2(v_[0], v_[1]);\n"
+                   << "      P_ = make_float2(P_.x * u_.x - P_.y * u_.y, P_.x * u_.y + P_.y * u_.x); }\n";
+            }
+            // register qubits: a[k] = P_ * prod_r v_r[bit r of k], built as a doubling tree
+            o_ << "    a[0] = P_;\n";
+            for (int r = 0; r < kRegBits; ++r) {
+                const int q = W_ - 1 - reg_shift[r];
+                o_ << "    { const float* v_ = " << vq(q) << ";\n"
+                   << "      const f2 u0_ = make_float2(v_[0], v_[1]), u1_ = make_float2(v_[4], v_[5]);\n";
+                for (int k = (1 << r) - 1; k >= 0; --k) {
+                    const int k1 = k | (1 << r);
+                    o_ << "      a[" << k1 << "] = make_float2(a[" << k << "].x * u1_.x - a[" << k << "].y * u1_.y, a["
+                       << k << "].x * u1_.y + a[" << k << "].y * u1_.x);\n"
+                       << "      a[" << k << "] = make_float2(a[" << k << "].x * u0_.x - a[" << k << "].y * u0_.y, a["
+                       << k << "].x * u0_.y + a[" << k << "].y * u0_.x);\n";
+                }
+                o_ << "    }\n";
+            }
+            o_ << "  }\n";
+        } else if (!bwd_) {
             o_ << "  f2* st = state + off;\n  " << act(gload("a", "st")) << "\n";
         } else if (flags & PF_FIRST_BWD) {
             o_ << "  " << act(gload("ps", "(psiN + off)")) << "\n";

@@ -856,7 +856,7 @@ int build_plan(qsv_plan_t* p) {
         auto passes = pack_passes(p, split_with(p, body, o.fuse_width), m, c, 1 << 30, dense);
         PassBuilder pb{p, false, {}};
         for (size_t i = 0; i < passes.size(); ++i)
-            pb.build(passes[i], dense[i], m, c, 0, p->fwd_pass, p->fwd_order);
+            pb.build(passes[i], dense[i], m, c, i == 0 ? PF_INIT_FWD : 0, p->fwd_pass, p->fwd_order);
     }
     {
         std::vector<uint32_t> dense;

@@ -1797,7 +1797,9 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
         HIP_TRY(hipGetLastError());
         return QSV_OK;
     }
-    if ((rc = run_init(p, T, mats, B, st, s))) return rc;
+    // generated forward kernels build the product state in their first pass
+    const bool fused_init = !T->fwd_fn.empty() && !p->fwd_pass.empty() && (p->fwd_pass[0].flags & PF_INIT_FWD);
+    if (!fused_init && (rc = run_init(p, T, mats, B, st, s))) return rc;
     const int W = p->W;
     const double amps = (double)B * (double)(int64_t(1) << W);
     if (p->opts.method == QSV_METHOD_PER_GATE) {
@@ -1834,7 +1836,8 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
                                T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
                                p->n_ps_mats, st, W);
         }
-        prof_end(p, s, ev, K_PASS_FWD, 16.0 * amps, p->fwd_pass_flops[i] * amps,
+        // a first pass that builds the initial state reads nothing
+        prof_end(p, s, ev, K_PASS_FWD, (fused_init && i == 0 ? 8.0 : 16.0) * amps, p->fwd_pass_flops[i] * amps,
                  T->fwd_fn.empty() ? -1 : (int)i);
     }
     HIP_TRY(hipGetLastError());
