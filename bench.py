@@ -124,8 +124,7 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
 
     def step(r):
         w, x = ws_inputs[r % n]
-        plan.forward(w, x, B, state)
-        plan.expval(state, E)
+        plan.forward_expval(w, x, B, state, E)
         plan.backward(w, x, state, g, gw=gw, gx=gx)
 
     for r in range(warmup):
@@ -202,8 +201,7 @@ def bench_uneven(args, torch, dev, binding, inputs):
     stream.synchronize()
     gms = t0.elapsed_time(t1) / args.uneven_steps
     # the last replay against eager calls on the same weights
-    st_e = plan.forward(runs[-1], xbuf, 1)
-    E_e = plan.expval(st_e)
+    st_e, E_e = plan.forward_expval(runs[-1], xbuf, 1)
     torch.cuda.synchronize()
     same = bool(torch.equal(E_e, E))
     del graph

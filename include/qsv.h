@@ -89,8 +89,9 @@ enum {
     QSV_METHOD_PER_GATE = 1 /* the plain method: one strided sweep of the state per gate */
 };
 
-/* workspace queries; QSV_OP_STEP = forward + readout + backward (qsv_graph_create) */
-enum { QSV_OP_FORWARD = 0, QSV_OP_EXPVAL = 1, QSV_OP_BACKWARD = 2, QSV_OP_STEP = 3 };
+/* workspace queries; QSV_OP_STEP = forward + readout + backward (qsv_graph_create),
+   QSV_OP_FORWARD_EXPVAL = qsv_forward_expval */
+enum { QSV_OP_FORWARD = 0, QSV_OP_EXPVAL = 1, QSV_OP_BACKWARD = 2, QSV_OP_STEP = 3, QSV_OP_FORWARD_EXPVAL = 4 };
 
 typedef struct {
     int32_t kind;  /* QSV_H ... QSV_CCRX */
@@ -229,6 +230,21 @@ int qsv_expval(const qsv_plan_t* plan, const void* d_state, int64_t batch, doubl
                void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * Forward and readout in one call: the same d_state as qsv_forward and the
+ * same d_out as qsv_expval (the circuit of section "State Vector
+ * Simulation" followed by the measurement layer of section "Hybrid Machine
+ * Learning"). With generated kernels (fused method, codegen on) the last
+ * forward pass sums |a|^2 (1 - 2 bit) over its tile while the amplitudes are
+ * still in registers, so the state is not read back; every other plan runs
+ * qsv_forward then qsv_expval. d_ws must hold qsv_workspace_size(plan, batch,
+ * QSV_OP_FORWARD_EXPVAL) bytes. Errors as for qsv_forward; d_out may not be
+ * NULL.
+ */
+int qsv_forward_expval(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
+                       int64_t batch, void* d_state, double* d_out, void* d_ws, size_t ws_bytes,
+                       void* stream);
+
+/*
  * Adjoint backward of L = sum_{b,i} g[b,i] E[b,i], g = d_grad_out (batch x W
  * float64). d_state holds psi_N from qsv_forward with the same weights and
  * inputs; it is read, not modified. Going back over the gates, the angle
@@ -307,7 +323,7 @@ int qsv_profile_enable(qsv_plan_t* plan, int32_t on);
 int qsv_profile_read(qsv_plan_t* plan, qsv_kernel_stat* out, int32_t max_out, int32_t* n_out);
 
 /*
- * HIP-graph capture of one step: qsv_forward, qsv_expval and (if d_grad_out
+ * HIP-graph capture of one step: qsv_forward_expval and (if d_grad_out
  * is not NULL) qsv_backward with these pointers are recorded once on
  * `stream` (a non-default hipStream_t) into a graph; qsv_graph_launch then
  * replays the whole launch sequence with one call. Pointers are fixed in the

@@ -23,7 +23,7 @@ KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "C
         "CRY": 10, "CRZ": 11, "CCX": 12, "CCZ": 13, "CCRX": 14}
 SRC = {"none": 0, "weight": 1, "input": 2}
 METHOD = {"fused": 0, "per_gate": 1}
-OP_FORWARD, OP_EXPVAL, OP_BACKWARD, OP_STEP = 0, 1, 2, 3
+OP_FORWARD, OP_EXPVAL, OP_BACKWARD, OP_STEP, OP_FORWARD_EXPVAL = 0, 1, 2, 3, 4
 
 ERR_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_QUBIT", -3: "QSV_ERR_GATE",
              -4: "QSV_ERR_PARAM", -5: "QSV_ERR_TOO_BIG", -6: "QSV_ERR_OOM", -7: "QSV_ERR_HIP",
@@ -71,7 +71,7 @@ class qsv_kernel_stat(ctypes.Structure):
 
 EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets",
            "qsv_plan_destroy", "qsv_workspace_size",
-           "qsv_forward", "qsv_expval", "qsv_backward", "qsv_plan_get_info",
+           "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
            "qsv_plan_codegen_check", "qsv_plan_estimate", "qsv_graph_create", "qsv_graph_launch",
            "qsv_graph_destroy", "qsv_profile_enable",
@@ -107,6 +107,8 @@ def lib():
         L.qsv_forward.restype = ctypes.c_int
         L.qsv_expval.argtypes = [vp, vp, i64, vp, vp, sz, vp]
         L.qsv_expval.restype = ctypes.c_int
+        L.qsv_forward_expval.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
+        L.qsv_forward_expval.restype = ctypes.c_int
         L.qsv_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp, vp, vp]
         L.qsv_backward.restype = ctypes.c_int
         L.qsv_plan_get_info.argtypes = [vp, ctypes.POINTER(qsv_plan_info)]
@@ -212,6 +214,11 @@ def qsv_forward(h, d_weights, d_inputs, batch, d_state, d_ws, ws_bytes, stream):
 
 def qsv_expval(h, d_state, batch, d_out, d_ws, ws_bytes, stream):
     return _check(lib().qsv_expval(h, d_state, int(batch), d_out, d_ws, int(ws_bytes), stream))
+
+
+def qsv_forward_expval(h, d_weights, d_inputs, batch, d_state, d_out, d_ws, ws_bytes, stream):
+    return _check(lib().qsv_forward_expval(h, d_weights, d_inputs, int(batch), d_state, d_out, d_ws,
+                                           int(ws_bytes), stream))
 
 
 def qsv_backward(h, d_weights, d_inputs, batch, d_state, d_grad_out, d_ws, ws_bytes,
@@ -413,6 +420,19 @@ class Plan:
         qsv_expval(self.handle, self._ptr(state), batch, self._ptr(out), self._ptr(ws), ws.numel(),
                    self._stream(state.device))
         return out
+
+    def forward_expval(self, weights, inputs, batch, state=None, out=None):
+        """forward() and expval() in one call -> (state, E)."""
+        import torch
+        dev = weights.device if weights is not None and weights.numel() else inputs.device
+        if state is None:
+            state = torch.empty((batch, self.state_len), dtype=torch.complex64, device=dev)
+        if out is None:
+            out = torch.empty((batch, self.n_out), dtype=torch.float64, device=dev)
+        ws = self.workspace(batch, OP_FORWARD_EXPVAL, dev)
+        qsv_forward_expval(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
+                           self._ptr(state), self._ptr(out), self._ptr(ws), ws.numel(), self._stream(dev))
+        return state, out
 
     def backward(self, weights, inputs, state, grad_out, want_inputs=True, gw=None, gx=None):
         import torch

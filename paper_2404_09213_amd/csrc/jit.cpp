@@ -159,6 +159,7 @@ __device__ __forceinline__ f2 qsv_flip(f2 a, unsigned s) {
         name = std::string(which == 0 ? "qsv_f" : "qsv_b") + I(i);
         o_.str("");
         bwd_ = which == 1;
+        last_fwd_ = which == 0 && i + 1 == (int)p_->fwd_pass.size();
         ps_ = &ps;
         m_ = ps.m;
         W_ = p_->W;
@@ -174,7 +175,8 @@ private:
     const qsv_plan_t* p_;
     const DPass* ps_ = nullptr;
     std::ostringstream o_;
-    bool bwd_ = false, guard_ = false;
+    bool bwd_ = false, guard_ = false, last_fwd_ = false;
+    std::string name_;
     int m_ = 0, W_ = 0, T_ = 0, threads_ = 0;
     std::vector<std::string> arrays_;
 
@@ -475,8 +477,67 @@ private:
         o_ << "    " << gs << " = ga_ + gb_;\n  }\n";
     }
 
+    // Readout of the last forward pass (when epart is given): per tile and
+    // qubit i, sum |a|^2 (1 - 2 bit_i) into epart[(b ntiles + tile) W + i].
+    // Reduced values: the thread's total T, its sums S_r over registers with
+    // register bit r set, and T on threads with thread-index bit j set; the
+    // out-of-tile qubits take the tile total with the tile's sign.
+    void emit_readout(const Layout& L) {
+        const int nreg = kRegBits, ntb = (int)L.nonreg.size();
+        const int nv = 1 + nreg + ntb, nw = threads_ / 64;
+        o_ << "  if (epart) {\n    __shared__ double ered_[" << nw * nv << "];\n";
+        o_ << "    float T_ = 0.f, S_[" << nreg << "] = {0.f, 0.f, 0.f, 0.f};\n";
+        o_ << "    if (" << (guard_ ? "act" : "true") << ") {\n";
+        for (int k = 0; k < kRegs; ++k) {
+            o_ << "      { const float p_ = a[" << k << "].x * a[" << k << "].x + a[" << k << "].y * a[" << k
+               << "].y; T_ += p_;";
+            for (int r = 0; r < nreg; ++r)
+                if (k >> r & 1) o_ << " S_[" << r << "] += p_;";
+            o_ << " }\n";
+        }
+        o_ << "    }\n";
+        o_ << "    double v_[" << nv << "];\n    v_[0] = T_;\n";
+        for (int r = 0; r < nreg; ++r) o_ << "    v_[" << 1 + r << "] = S_[" << r << "];\n";
+        for (int j = 0; j < ntb; ++j)
+            o_ << "    v_[" << 1 + nreg + j << "] = ((t >> " << j << ") & 1) ? (double)T_ : 0.0;\n";
+        o_ << "    for (int k = 0; k < " << nv << "; ++k) { const double r_ = qsv_wave_sum(v_[k]); "
+           << "if (lane == 0) ered_[wave * " << nv << " + k] = r_; }\n";
+        o_ << "    __syncthreads();\n";
+        o_ << "    const int* eq_ = " << name_ << "_eq;\n";
+        o_ << "    for (int i = t; i < " << W_ << "; i += " << threads_ << ") {\n"
+           << "      double tot = 0.0, part_ = 0.0;\n"
+           << "      for (int w = 0; w < " << nw << "; ++w) { tot += ered_[w * " << nv << "]; "
+           << "if (eq_[2 * i] != 2) part_ += ered_[w * " << nv << " + eq_[2 * i + 1]]; }\n"
+           << "      const double e = eq_[2 * i] == 2 ? (((base >> eq_[2 * i + 1]) & 1) ? -tot : tot)"
+           << " : tot - 2.0 * part_;\n"
+           << "      epart[((size_t)b * " << (1u << (W_ - m_)) << "u + tis) * " << W_ << " + i] = e;\n    }\n  }\n";
+    }
+
+    // per qubit of the readout: kind (0 register bit, 1 thread bit, 2 out-of-tile)
+    // and the reduced value's index (kinds 0, 1) or the index-bit shift (kind 2)
+    std::string readout_table(const Layout& L) const {
+        std::ostringstream e;
+        e << "__device__ const int " << name_ << "_eq[" << 2 * W_ << "] = {";
+        for (int i = 0; i < W_; ++i) {
+            const int sh = W_ - 1 - i;
+            int kind = 2, idx = sh;
+            for (int r = 0; r < kRegBits; ++r)
+                if (lq(L.reg[r]) == sh) { kind = 0; idx = 1 + r; }
+            for (int j = 0; j < (int)L.nonreg.size(); ++j)
+                if (lq(L.nonreg[j]) == sh) { kind = 1; idx = 1 + kRegBits + j; }
+            e << (i ? "," : "") << kind << "," << idx;
+        }
+        e << "};\n";
+        return e.str();
+    }
+
     void emit_kernel(const std::string& name) {
+        name_ = name;
         const int tb = W_ - m_;
+        if (last_fwd_) {
+            const int nat_reg0[kRegBits] = {m_ - 4, m_ - 3, m_ - 2, m_ - 1};
+            o_ << readout_table(make_layout(m_, nat_reg0));
+        }
         if (bwd_ && ps_->n_gout) {
             // gradient outputs of this pass: ordinal, axis, component slots x/y/z, matrix slot
             o_ << "__device__ const int " << name << "_out[" << 6 * ps_->n_gout << "] = {";
@@ -493,7 +554,8 @@ private:
                   "const double* __restrict__ gout, const float* __restrict__ mats, int n_shared, int n_ps, "
                   "double* __restrict__ part, int B)\n{\n";
         else
-            o_ << "f2* __restrict__ state, const float* __restrict__ mats, int n_shared, int n_ps)\n{\n";
+            o_ << "f2* __restrict__ state, const float* __restrict__ mats, int n_shared, int n_ps"
+               << (last_fwd_ ? ", double* __restrict__ epart" : "") << ")\n{\n";
         o_ << "  __shared__ f2 lds[" << (1 << m_) << "];\n";
         int ng = bwd_ ? ps_->n_gslots : 0;
         const int nw = threads_ / 64;
@@ -624,6 +686,7 @@ private:
             if (!bwd_) o_ << "  " << act(gstore("a", "st")) << "\n";
             else o_ << "  " << act(gstore("ps", "(psi + off)") + gstore("lm", "(lam + off)")) << "\n";
         }
+        if (last_fwd_) emit_readout(cur);
         if (bwd_ && ng) {
             o_ << "  __syncthreads();\n";
             o_ << "  {\n    __shared__ double cs_[" << ng << "];\n";

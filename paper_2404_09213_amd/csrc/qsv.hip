@@ -1751,22 +1751,31 @@ size_t qsv_workspace_size(const qsv_plan_t* p, int64_t B, int32_t op) {
     case QSV_OP_BACKWARD:
         return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + partial_bytes(p, B);
     case QSV_OP_STEP:
-        return qsv_workspace_size(p, B, QSV_OP_BACKWARD) + qsv_workspace_size(p, B, QSV_OP_EXPVAL);
+        return std::max(qsv_workspace_size(p, B, QSV_OP_BACKWARD), qsv_workspace_size(p, B, QSV_OP_FORWARD_EXPVAL));
+    case QSV_OP_FORWARD_EXPVAL: {
+        // forward matrices, then readout partials: per generated tile (fused
+        // readout) or per readout chunk, whichever is more
+        size_t part = qsv_workspace_size(p, B, QSV_OP_EXPVAL);
+        if (!p->multi)
+            part = std::max(part, align256((size_t)B * ((size_t)1 << (p->W - std::min(p->opts.tile_qubits, p->W))) *
+                                           p->W * sizeof(double)));
+        return mats_bytes(p, B) + part;
+    }
     default: return 0;
     }
 }
 
-int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
-                void* ws, size_t ws_bytes, void* stream) {
-    int rc = check_plan(p);
-    if (rc) return rc;
-    if ((rc = check_batch(p, B))) return rc;
-    if (!d_state || (p->n_weights && !w) || (p->n_inputs && !x)) { set_error("null pointer"); return QSV_ERR_ARG; }
-    const size_t need = qsv_workspace_size(p, B, QSV_OP_FORWARD);
-    if (!ws || ws_bytes < need) { set_error("forward workspace too small"); return QSV_ERR_ARG; }
-    hipStream_t s = (hipStream_t)stream;
-    DeviceTables* T;
-    if ((rc = get_tables(p, &T))) return rc;
+// true when the last generated forward kernel can write the readout partials
+// itself: fused method, generated kernels, at least one pass
+static bool fused_readout(const qsv_plan_t* p, const DeviceTables* T) {
+    return !p->multi && p->opts.method != QSV_METHOD_PER_GATE && !T->fwd_fn.empty() && !p->fwd_pass.empty();
+}
+
+// Forward over validated arguments. epart (used only when fused_readout())
+// receives the per-tile readout partials [b][tile][i] of the final state.
+static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
+                        void* ws, hipStream_t s, DeviceTables* T, double* epart) {
+    int rc;
     float* mats = (float*)ws;
     float2* st = (float2*)d_state;
     if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
@@ -1828,7 +1837,8 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
         if (!T->fwd_fn.empty()) {
             int ns = p->n_shared_mats, np = p->n_ps_mats;
             const float* mp = mats;
-            void* args[] = {&st, &mp, &ns, &np};
+            double* ep = epart;
+            void* args[] = {&st, &mp, &ns, &np, &ep};  // the last pass takes the readout pointer
             HIP_TRY(hipModuleLaunchKernel((hipFunction_t)T->fwd_fn[i], tiles, 1, 1, threads, 1, 1, 0,
                                           s, args, nullptr));
         } else {
@@ -1836,10 +1846,57 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
                                T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
                                p->n_ps_mats, st, W);
         }
-        // a first pass that builds the initial state reads nothing
-        prof_end(p, s, ev, K_PASS_FWD, (fused_init && i == 0 ? 8.0 : 16.0) * amps, p->fwd_pass_flops[i] * amps,
-                 T->fwd_fn.empty() ? -1 : (int)i);
+        // a first pass that builds the initial state reads nothing; a last pass
+        // with the readout adds its partials
+        double bytes = (fused_init && i == 0 ? 8.0 : 16.0) * amps;
+        if (epart && i + 1 == p->fwd_pass.size()) bytes += 8.0 * (double)tiles * W;
+        prof_end(p, s, ev, K_PASS_FWD, bytes, p->fwd_pass_flops[i] * amps, T->fwd_fn.empty() ? -1 : (int)i);
     }
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
+}
+
+int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
+                void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!d_state || (p->n_weights && !w) || (p->n_inputs && !x)) { set_error("null pointer"); return QSV_ERR_ARG; }
+    const size_t need = qsv_workspace_size(p, B, QSV_OP_FORWARD);
+    if (!ws || ws_bytes < need) { set_error("forward workspace too small"); return QSV_ERR_ARG; }
+    DeviceTables* T;
+    if ((rc = get_tables(p, &T))) return rc;
+    return forward_impl(p, w, x, B, d_state, ws, (hipStream_t)stream, T, nullptr);
+}
+
+int qsv_forward_expval(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
+                       double* out, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!d_state || !out || (p->n_weights && !w) || (p->n_inputs && !x)) {
+        set_error("null pointer");
+        return QSV_ERR_ARG;
+    }
+    const size_t need = qsv_workspace_size(p, B, QSV_OP_FORWARD_EXPVAL);
+    if (!ws || ws_bytes < need) { set_error("forward_expval workspace too small"); return QSV_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    DeviceTables* T;
+    if ((rc = get_tables(p, &T))) return rc;
+    const size_t fwd_bytes = qsv_workspace_size(p, B, QSV_OP_FORWARD);
+    char* wsc = (char*)ws;
+    if (!fused_readout(p, T)) {
+        rc = forward_impl(p, w, x, B, d_state, ws, s, T, nullptr);
+        if (!rc) rc = qsv_expval(p, d_state, B, out, wsc + fwd_bytes, ws_bytes - fwd_bytes, stream);
+        return rc;
+    }
+    double* part = (double*)(wsc + fwd_bytes);
+    if ((rc = forward_impl(p, w, x, B, d_state, ws, s, T, part))) return rc;
+    const int64_t ntiles = int64_t(1) << (p->W - std::min(p->opts.tile_qubits, p->W));
+    hipEvent_t ev = prof_begin(p, s);
+    hipLaunchKernelGGL(k_expval_final, dim3((unsigned)p->W, (unsigned)B), dim3(256), 0, s, (const double*)part,
+                       p->W, ntiles, out);
+    prof_end(p, s, ev, K_EXPVAL_FINAL, 8.0 * (double)B * ntiles * p->W, 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }
@@ -2098,8 +2155,8 @@ int qsv_graph_create(const qsv_plan_t* p, int64_t B, const float* w, const float
     char* wsc = (char*)ws;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     g_capturing = true;
-    rc = qsv_forward(p, w, x, B, d_state, wsc, bwd_bytes, stream);
-    if (!rc) rc = qsv_expval(p, d_state, B, d_expval, wsc + bwd_bytes, ws_bytes - bwd_bytes, stream);
+    // forward with readout, then the backward over the same workspace (stream order)
+    rc = qsv_forward_expval(p, w, x, B, d_state, d_expval, wsc, ws_bytes, stream);
     if (!rc && gout) rc = qsv_backward(p, w, x, B, d_state, gout, wsc, bwd_bytes, gw, gx, stream);
     g_capturing = false;
     hipGraph_t graph = nullptr;

@@ -2,7 +2,7 @@
 holding the quantum weights as Parameters (section "API": circuits behave like
 ordinary torch.nn.Modules, weights reachable through .parameters()).
 
-Forward: qsv_forward then qsv_expval -> (B, W) float64 expectations.
+Forward: qsv_forward_expval -> (B, W) float64 expectations (and psi_N).
 Backward: qsv_backward (adjoint method; psi_N saved from the forward).
 """
 from __future__ import annotations
@@ -20,8 +20,7 @@ class QsvFunction(torch.autograd.Function):
     def forward(ctx, weights, x, plan):
         w32 = weights.detach().to(torch.float32).contiguous()
         x32 = x.detach().to(torch.float32).contiguous()
-        state = plan.forward(w32, x32, x32.shape[0])
-        E = plan.expval(state)
+        state, E = plan.forward_expval(w32, x32, x32.shape[0])
         ctx.plan = plan
         ctx.save_for_backward(w32, x32, state)
         ctx.dtypes = (weights.dtype, x.dtype)

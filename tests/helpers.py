@@ -36,7 +36,13 @@ def gpu_run(circ, w, x, batch, g=None, method="fused", **opts):
     xt = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
     st = plan.forward(wt, xt, batch)
     E = plan.expval(st)
-    out = {"state": st, "E": E, "plan": plan}
+    # the one-call forward + readout gives the same state and the readout up
+    # to the summation order of the float32 per-thread partials
+    st2, E2 = plan.forward_expval(wt, xt, batch)
+    assert torch.equal(st2, st), "forward_expval state differs from forward"
+    assert (E2 - E).abs().max().item() <= EXP_TOL / 10 if E.numel() else True
+    del st2
+    out = {"state": st, "E": E, "E_fused": E2, "plan": plan}
     if g is not None:
         gw, gx = plan.backward(wt, xt, st, torch.from_numpy(np.ascontiguousarray(g)).to(dev))
         out["gw"], out["gx"] = gw, gx

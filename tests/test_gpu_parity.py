@@ -40,8 +40,10 @@ def _check(circ, batch, seed, orc, method, grads=True, **opts):
     ref = oracle_run(orc, circ, w, x, batch, g)
     amp = np.abs(got["state"].cpu().numpy() - ref["state"]).max()
     e = np.abs(got["E"].cpu().numpy() - ref["E"]).max()
+    e2 = np.abs(got["E_fused"].cpu().numpy() - ref["E"]).max()
     assert amp <= AMP_TOL, amp
     assert e <= EXP_TOL, e
+    assert e2 <= EXP_TOL, ("forward_expval", e2)
     if grads:
         ok, rel = grad_close(got["gw"].cpu().numpy(), ref["gw"])
         assert ok, ("weights", rel)
@@ -152,6 +154,7 @@ def _sampled_full_size(orc, name, method, samples):
     st = got["state"].cpu().numpy()[samples]
     assert np.abs(st - ref["state"]).max() <= AMP_TOL
     assert np.abs(got["E"].cpu().numpy()[samples] - ref["E"]).max() <= EXP_TOL
+    assert np.abs(got["E_fused"].cpu().numpy()[samples] - ref["E"]).max() <= EXP_TOL
     ok, rel = grad_close(got["gw"].cpu().numpy(), ref["gw"])
     assert ok, ("weights", rel)
     ok, rel = grad_close(got["gx"].cpu().numpy()[samples], ref["gx"])

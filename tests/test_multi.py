@@ -93,6 +93,10 @@ def _run_multi(cs, batch, seed, orc, check_ids=None, **opts):
     print("[multi] expval", flush=True)
     E = mp.expval(st)
     torch.cuda.synchronize()
+    print("[multi] forward_expval", flush=True)
+    st2, E2 = mp.forward_expval(wt, xt, batch)
+    assert torch.equal(st2, st) and torch.equal(E2, E)
+    del st2, E2
     print("[multi] backward", flush=True)
     gw, gx = mp.backward(wt, xt, st, torch.from_numpy(g).to(dev))
     torch.cuda.synchronize()
