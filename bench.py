@@ -56,25 +56,31 @@ def parse():
     return ap.parse_args()
 
 
-def copy_calibration(args):
-    """A plain device-to-device copy of 1 GiB, three times: the reference for
-    scaling rocprofv3's FETCH_SIZE / WRITE_SIZE to bytes."""
+def copy_rate(reps=5):
+    """A plain device-to-device copy of 1 GiB, `reps` times: read + write bytes
+    over the best time, the on-box reference rate for HBM-bound kernels."""
     import torch
     n = 1 << 28  # float32 elements = 1 GiB
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     ms = []
-    for _ in range(3):
+    for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         b.copy_(a)
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
-    print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
-                      "ms": [round(x, 4) for x in ms],
-                      "gbs": round(8 * n / (min(ms) / 1e3) / 1e9, 1)}), flush=True)
+    del a, b
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": [round(x, 4) for x in ms],
+            "gbs": round(8 * n / (min(ms) / 1e3) / 1e9, 1)}
+
+
+def copy_calibration(args):
+    """The copy above as its own run: the reference for scaling rocprofv3's
+    FETCH_SIZE / WRITE_SIZE to bytes."""
+    print(json.dumps(dict(mode="copy", **copy_rate())), flush=True)
 
 
 def family(name):
@@ -284,10 +290,18 @@ def main():
     if args.per_gate_steps > 0:
         pms, pstats = run_steps(per_gate, runs, g, state, E, gw, gx, args.per_gate_steps, 1, torch)
         pbytes = sum(v["bytes"] for v in pstats.values()) / args.per_gate_steps
+        copy_gbs = copy_rate()["gbs"]
         pg = {"ms_per_step": round(pms, 3), "evals_per_s": round(B / (pms / 1e3), 2),
               "hbm_gbs": round(pbytes / (pms / 1e3) / 1e9, 1),
               "hbm_frac": round(pbytes / (pms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-              "launches_per_step": int(sum(v["launches"] for v in pstats.values()) // args.per_gate_steps)}
+              "launches_per_step": int(sum(v["launches"] for v in pstats.values()) // args.per_gate_steps),
+              "copy_gbs": copy_gbs,
+              # per gate class: algorithmic GB/s, as a fraction of the 8 TB/s peak and of the copy
+              "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                              "gbs": round(v["bytes"] / (v["total_ms"] / 1e3) / 1e9, 1),
+                              "hbm_frac": round(v["bytes"] / (v["total_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "copy_frac": round(v["bytes"] / (v["total_ms"] / 1e3) / 1e9 / copy_gbs, 4)}
+                          for k, v in sorted(pstats.items()) if v["total_ms"] > 0}}
         log(args, f"[bench] per-gate: {pms:.3f} ms/step  {pg}")
 
     uneven = bench_uneven(args, torch, dev, binding, inputs) if args.uneven_steps > 0 else None
@@ -311,7 +325,6 @@ def main():
                  "alg_bytes_per_launch": dom["bytes"] / dom["launches"],
                  "alg_flops_per_launch": dom["flops"] / dom["launches"],
                  "hbm_frac": round(hbm_frac, 4), "alu_frac": round(alu_frac, 4),
-                 "alu_frac_nonpacked": round(tfs / (FP32_VECTOR_PEAK_TF / 2), 4),
                  "family": family(dom_name),
                  "family_ms_per_step": round(dfam["total_ms"] / args.steps, 4),
                  "family_alu_tflops": round(dfam["flops"] / (dfam["total_ms"] / 1e3) / 1e12, 3),

@@ -29,10 +29,10 @@
  * qsv_plan_destroy). Workspaces are caller memory of at least
  * qsv_workspace_size() bytes, 256-byte aligned.
  *
- * Asynchrony: qsv_forward / qsv_expval / qsv_backward validate on the host,
- * then enqueue kernels on `stream` (a hipStream_t, NULL = default stream)
- * and return; faults show at the caller's next synchronisation. On a
- * non-zero return nothing was enqueued.
+ * Asynchrony: qsv_forward / qsv_forward_expval / qsv_expval / qsv_backward
+ * validate on the host, then enqueue kernels on `stream` (a hipStream_t,
+ * NULL = default stream) and return; faults show at the caller's next
+ * synchronisation. On a non-zero return nothing was enqueued.
  *
  * Errors: functions return 0 or a negative QSV_ERR_* code; qsv_last_error()
  * gives a thread-local message for the last failure in this thread.
@@ -126,8 +126,9 @@ typedef struct {
     int32_t mfma;        /* generated kernels: generic 2x2 products on the matrix
                             cores (v_mfma_f32_4x4x1_16b: each lane multiplies its own
                             amplitude pair, as a real 4-vector, by the gate's real 4x4
-                            form) in 1 (default): forward kernels, 2: forward and
-                            backward kernels; 0: everything on the vector ALU */
+                            form). Bit mask, 0..7: 1 forward kernels (default 1),
+                            2 backward psi, 4 backward lambda; 0 = everything on the
+                            vector ALU */
     int32_t weight_remap; /* 1: every weight angle w enters its gate as pi tanh(w)
                             (quantum weight remapping, section "Additional
                             Optimizations": weights mapped into (-pi, pi) by tanh);
@@ -299,17 +300,20 @@ int qsv_plan_codegen_check(const qsv_plan_t* plan, const char* arch);
 
 /*
  * Kernel profiling. While enabled, every kernel launch made by qsv_forward,
- * qsv_expval and qsv_backward with this plan is bracketed by two HIP events
- * recorded on the call's stream, and the launch's algorithmic traffic and
- * arithmetic are noted:
+ * qsv_forward_expval, qsv_expval and qsv_backward with this plan is bracketed
+ * by two HIP events recorded on the call's stream, and the launch's
+ * algorithmic traffic and arithmetic are noted:
  *   bytes = 8 bytes per amplitude read or written (complex64) by the
  *           method's definition of the step, not by the cache hierarchy;
  *   flops = float32 operations of the gate arithmetic (complex multiply = 6).
  * qsv_profile_read waits for the recorded events, writes up to max_out
  * per-kernel totals, sets *n_out, and clears the record. Kernels generated
  * for a plan get one entry per pass under their symbol names ("qsv_f<i>",
- * "qsv_b<i>"); library kernels one entry per kernel. Enabling or reading
- * while another thread calls into the same plan is not supported.
+ * "qsv_b<i>"); the per-gate method's kernels one entry per gate class
+ * ("k_pg_apply.1q", ".diag", ".ctl" for controlled gates, ".sign" for CZ / Z /
+ * CCZ; likewise "k_pg_adj.*"); other library kernels one entry per kernel.
+ * Enabling or reading while another thread calls into the same plan is not
+ * supported.
  */
 typedef struct {
     char name[32];

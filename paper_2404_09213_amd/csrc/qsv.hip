@@ -381,43 +381,64 @@ __device__ __forceinline__ bool pg_ctl_ok(const PGate& pg, int64_t idx) {
 __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, int W, int64_t B,
                                                   PGate pg, const float* __restrict__ mats,
                                                   int n_shared, int n_ps) {
+    // kPgItems items per thread, 256 apart (coalesced). Items touch disjoint
+    // amplitudes, so every load of the thread is issued before the first store:
+    // several loads in flight per thread instead of one item at a time.
     const int64_t base = ((int64_t)blockIdx.x * kPgItems) * 256 + threadIdx.x;
     if (pg.cls == OP_DIAG) {
         const int64_t total = B << W;
+        float2 a[kPgItems];
+#pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
-            if (it >= total) return;
-            if (!pg_ctl_ok(pg, it)) continue;
+            if (it < total && pg_ctl_ok(pg, it)) a[i] = state[it];
+        }
+#pragma unroll
+        for (int i = 0; i < kPgItems; ++i) {
+            const int64_t it = base + i * 256;
+            if (it >= total || !pg_ctl_ok(pg, it)) continue;
             const int b = (int)(it >> W);
             const M2 M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
             const float2 ph = ((it >> pg.tsh) & 1) ? M.m11 : M.m00;
-            state[it] = cmul(ph, state[it]);
+            state[it] = cmul(ph, a[i]);
         }
     } else if (pg.cls == OP_SIGN) {
         const PgBits f = pg_bits(pg);
         const int64_t total = B << (W - f.n);
+        float2 a[kPgItems];
+        int64_t idx[kPgItems];
+#pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
-            if (it >= total) return;
-            const int64_t idx = pg_index(it, f);
-            const float2 a = state[idx];
-            state[idx] = make_float2(-a.x, -a.y);
+            idx[i] = it < total ? pg_index(it, f) : -1;
+            if (idx[i] >= 0) a[i] = state[idx[i]];
         }
+#pragma unroll
+        for (int i = 0; i < kPgItems; ++i)
+            if (idx[i] >= 0) state[idx[i]] = make_float2(-a[i].x, -a[i].y);
     } else {
         const PgBits f = pg_bits(pg);
         const int64_t total = B << (W - f.n);
+        const int64_t step = int64_t(1) << pg.tsh;
+        float2 x[kPgItems], y[kPgItems];
+        int64_t i0[kPgItems];
+#pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
-            if (it >= total) return;
-            const int64_t i0 = pg_index(it, f);
-            const int64_t i1 = i0 | (int64_t(1) << pg.tsh);
-            const int b = (int)(i0 >> W);
+            i0[i] = it < total ? pg_index(it, f) : -1;
+            if (i0[i] >= 0) {
+                x[i] = state[i0[i]];
+                y[i] = state[i0[i] | step];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kPgItems; ++i) {
+            if (i0[i] < 0) continue;
             M2 M{};
-            if (pg.cls != OP_SWAP) M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
-            float2 x = state[i0], y = state[i1];
-            pair_apply(pg.cls, M, x, y);
-            state[i0] = x;
-            state[i1] = y;
+            if (pg.cls != OP_SWAP) M = load_m2(mat_ptr(mats, pg.mat, (int)(i0[i] >> W), n_shared, n_ps));
+            pair_apply(pg.cls, M, x[i], y[i]);
+            state[i0[i]] = x[i];
+            state[i0[i] | step] = y[i];
         }
     }
 }
@@ -1542,6 +1563,16 @@ double pg_touched(const PGate& g) {
     return 1.0 / (double)(1 << nctl);
 }
 
+// profiling class of a per-gate launch: 0 dense 1-qubit, 1 diagonal, 2 controlled
+// (half or a quarter of the pairs), 3 sign (CZ / Z / CCZ on a fraction of the state)
+int pg_prof_class(const PGate& g) {
+    if (g.cls == OP_SIGN) return 3;
+    if (g.csh >= 0 || g.csh2 >= 0) return 2;
+    return g.cls == OP_DIAG ? 1 : 0;
+}
+constexpr int kPgSub0 = 1000;  // profiler sub-key offset of the per-gate classes
+const char* const kPgClassNames[4] = {"1q", "diag", "ctl", "sign"};
+
 size_t pass_lds_fwd(const qsv_plan_t* p) {
     const int m = std::min(p->opts.tile_qubits, p->W);
     return (size_t(1) << m) * 8;
@@ -1823,7 +1854,8 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
             hipEvent_t ev = prof_begin(p, s);
             hipLaunchKernelGGL(k_pg_apply, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
                                (const float*)mats, p->n_shared_mats, p->n_ps_mats);
-            prof_end(p, s, ev, K_PG_APPLY, 16.0 * touched * amps, p->pg_fwd_flops[i] * amps);
+            prof_end(p, s, ev, K_PG_APPLY, 16.0 * touched * amps, p->pg_fwd_flops[i] * amps,
+                     kPgSub0 + pg_prof_class(pg));
         }
         HIP_TRY(hipGetLastError());
         return QSV_OK;
@@ -2006,7 +2038,8 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
             hipLaunchKernelGGL(k_pg_adj, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi,
                                lam, W, (int)B, pg, (const float*)mats, p->n_shared_mats,
                                p->n_ps_mats, part, nch);
-            prof_end(p, s, ev, K_PG_ADJ, 32.0 * touched * amps, p->pg_bwd_flops[i] * amps);
+            prof_end(p, s, ev, K_PG_ADJ, 32.0 * touched * amps, p->pg_bwd_flops[i] * amps,
+                     kPgSub0 + pg_prof_class(pg));
         }
     } else {
         const int m = std::min(p->opts.tile_qubits, W);
@@ -2319,7 +2352,9 @@ int qsv_profile_read(qsv_plan_t* p, qsv_kernel_stat* out, int32_t max_out, int32
             if (it == tot.end()) {
                 qsv_kernel_stat z;
                 std::memset(&z, 0, sizeof z);
-                if (r.sub >= 0)  // the generated kernel's own symbol name
+                if (r.sub >= kPgSub0)  // per-gate kernel, split by gate class
+                    std::snprintf(z.name, sizeof z.name, "%s.%s", kKernelNames[r.kid], kPgClassNames[r.sub - kPgSub0]);
+                else if (r.sub >= 0)  // the generated kernel's own symbol name
                     std::snprintf(z.name, sizeof z.name, "qsv_%c%d", r.kid == K_PASS_FWD ? 'f' : 'b', r.sub);
                 else
                     std::snprintf(z.name, sizeof z.name, "%s", kKernelNames[r.kid]);
