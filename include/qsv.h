@@ -207,6 +207,12 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
 int qsv_plan_circuit_offsets(const qsv_plan_t* plan, int32_t circuit, int64_t* amp_offset,
                              int32_t* qubit_offset, int32_t* weight_offset, int32_t* input_offset);
 
+/* Byte offset of circuit `circuit`'s amplitudes within one sample's row of
+ * the state (8 bytes per complex64 amplitude; single plans: 0), or a
+ * negative QSV_ERR_* code (QSV_ERR_HANDLE, QSV_ERR_ARG for an index out of
+ * range). */
+int64_t qsv_state_offset(const qsv_plan_t* plan, int32_t circuit);
+
 /* Release a plan and its device tables. NULL is ignored. */
 void qsv_plan_destroy(qsv_plan_t* plan);
 

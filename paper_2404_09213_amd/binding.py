@@ -69,7 +69,7 @@ class qsv_kernel_stat(ctypes.Structure):
                 ("flops", ctypes.c_double)]
 
 
-EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets",
+EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets", "qsv_state_offset",
            "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
@@ -99,6 +99,8 @@ def lib():
         L.qsv_plan_circuit_offsets.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                                ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.qsv_plan_circuit_offsets.restype = ctypes.c_int
+        L.qsv_state_offset.argtypes = [vp, i32]
+        L.qsv_state_offset.restype = i64
         L.qsv_plan_destroy.argtypes = [vp]
         L.qsv_plan_destroy.restype = None
         L.qsv_workspace_size.argtypes = [vp, i64, i32]
@@ -197,6 +199,14 @@ def qsv_plan_circuit_offsets(h, circuit):
     _check(lib().qsv_plan_circuit_offsets(h, int(circuit), ctypes.byref(a), ctypes.byref(q),
                                           ctypes.byref(w), ctypes.byref(x)))
     return {"amp": a.value, "qubit": q.value, "weight": w.value, "input": x.value}
+
+
+def qsv_state_offset(h, circuit):
+    """Byte offset of a circuit's amplitudes within one sample's state row."""
+    v = int(lib().qsv_state_offset(h, int(circuit)))
+    if v < 0:
+        raise QsvError(v, lib().qsv_last_error().decode())
+    return v
 
 
 def qsv_plan_destroy(h):

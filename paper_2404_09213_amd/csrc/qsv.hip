@@ -2157,6 +2157,12 @@ int qsv_plan_circuit_offsets(const qsv_plan_t* p, int32_t circuit, int64_t* amp,
     return QSV_OK;
 }
 
+int64_t qsv_state_offset(const qsv_plan_t* p, int32_t circuit) {
+    int64_t amp = 0;
+    const int rc = qsv_plan_circuit_offsets(p, circuit, &amp, nullptr, nullptr, nullptr);
+    return rc ? (int64_t)rc : amp * (int64_t)sizeof(float2);
+}
+
 struct qsv_graph_s {
     uint32_t magic;
     hipGraph_t graph;

@@ -51,11 +51,17 @@ def test_multi_plan_layout_offsets():
     amp = q = w = x = 0
     for i, c in enumerate(cs):
         assert mp.offsets[i] == {"amp": amp, "qubit": q, "weight": w, "input": x}
+        assert B.qsv_state_offset(mp.handle, i) == 8 * amp  # bytes of complex64
         amp += 1 << c.n_qubits
         q += c.n_qubits
         w += c.n_weights
         x += c.n_inputs
     assert mp.state_len == amp
+    with pytest.raises(B.QsvError) as e:
+        B.qsv_state_offset(mp.handle, len(cs))
+    assert e.value.code == -1
+    single = B.Plan(cs[0].n_qubits, cs[0].gates, cs[0].n_weights, cs[0].n_inputs)
+    assert B.qsv_state_offset(single.handle, 0) == 0
 
 
 def test_multi_plan_rejects_small_and_invalid():
