@@ -20,8 +20,10 @@
  *    where c = 1. For 2-qubit gates q0 is the control, q1 the target.
  *  - State layout: sample-major (B, 2^W) complex64, interleaved (re, im) float
  *    pairs; amplitude idx of sample b at float offset 2 * (b * 2^W + idx).
+ *    Plans with amp_dtype = QSV_AMP_C128 use complex128 (interleaved double
+ *    pairs) in the same order.
  *  - Expectations and gradients are float64; amplitudes and gate arithmetic
- *    are float32.
+ *    are float32 (float64 with amp_dtype = QSV_AMP_C128).
  *
  * Ownership: every d_ pointer is device memory owned by the caller; the
  * library never frees it. A plan owns its host tables and the device copies
@@ -137,8 +139,16 @@ typedef struct {
                             "Circuit Splitting"); 1: list scheduling over the
                             dependency graph (the graph-based split named as future
                             work in section "Conclusion") */
-    int32_t reserved[2];
+    int32_t amp_dtype;   /* QSV_AMP_C64 (default): complex64 states, float32 gate
+                            arithmetic; QSV_AMP_C128: complex128 states and float64
+                            gate matrices, for the plain method only (method =
+                            QSV_METHOD_PER_GATE; the same kernels instantiated for
+                            double precision). State and workspace sizes double. */
+    int32_t reserved;
 } qsv_opts;
+
+/* amplitude types (qsv_opts.amp_dtype) */
+enum { QSV_AMP_C64 = 0, QSV_AMP_C128 = 1 };
 
 typedef struct {
     int32_t n_qubits, n_gates, n_weights, n_inputs;

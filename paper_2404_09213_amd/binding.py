@@ -24,6 +24,7 @@ KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "C
 SRC = {"none": 0, "weight": 1, "input": 2}
 METHOD = {"fused": 0, "per_gate": 1}
 OP_FORWARD, OP_EXPVAL, OP_BACKWARD, OP_STEP, OP_FORWARD_EXPVAL = 0, 1, 2, 3, 4
+AMP = {"c64": 0, "c128": 1}
 
 ERR_NAMES = {0: "QSV_OK", -1: "QSV_ERR_ARG", -2: "QSV_ERR_QUBIT", -3: "QSV_ERR_GATE",
              -4: "QSV_ERR_PARAM", -5: "QSV_ERR_TOO_BIG", -6: "QSV_ERR_OOM", -7: "QSV_ERR_HIP",
@@ -47,7 +48,7 @@ class qsv_opts(ctypes.Structure):
                 ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
                 ("bwd_gate_by_gate", ctypes.c_int32), ("mfma", ctypes.c_int32),
                 ("weight_remap", ctypes.c_int32), ("splitter", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("amp_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -332,8 +333,10 @@ def qsv_last_error():
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
               max_pass_grads=None, codegen=None, bwd_gate_by_gate=None, mfma=None,
-              weight_remap=None, splitter=None):
+              weight_remap=None, splitter=None, amp_dtype=None):
     o = qsv_default_opts()
+    if amp_dtype is not None:
+        o.amp_dtype = AMP[amp_dtype] if isinstance(amp_dtype, str) else int(amp_dtype)
     if splitter is not None:
         o.splitter = int(splitter)
     if weight_remap is not None:
@@ -379,6 +382,11 @@ class Plan:
     def info(self):
         return qsv_plan_get_info(self.handle)
 
+    def state_dtype(self):
+        """torch dtype of the plan's states: complex64, or complex128 (amp_dtype c128)."""
+        import torch
+        return torch.complex128 if self.opts.amp_dtype == AMP["c128"] else torch.complex64
+
     def gate_order(self, which):
         return qsv_plan_gate_order(self.handle, which, self.n_gates)
 
@@ -415,7 +423,7 @@ class Plan:
         import torch
         dev = weights.device if weights is not None and weights.numel() else inputs.device
         if state is None:
-            state = torch.empty((batch, self.state_len), dtype=torch.complex64, device=dev)
+            state = torch.empty((batch, self.state_len), dtype=self.state_dtype(), device=dev)
         ws = self.workspace(batch, OP_FORWARD, dev)
         qsv_forward(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
                     self._ptr(state), self._ptr(ws), ws.numel(), self._stream(dev))
@@ -436,7 +444,7 @@ class Plan:
         import torch
         dev = weights.device if weights is not None and weights.numel() else inputs.device
         if state is None:
-            state = torch.empty((batch, self.state_len), dtype=torch.complex64, device=dev)
+            state = torch.empty((batch, self.state_len), dtype=self.state_dtype(), device=dev)
         if out is None:
             out = torch.empty((batch, self.n_out), dtype=torch.float64, device=dev)
         ws = self.workspace(batch, OP_FORWARD_EXPVAL, dev)

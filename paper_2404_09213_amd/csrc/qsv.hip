@@ -50,21 +50,40 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 
-struct M2 { float2 m00, m01, m10, m11; };
+// Amplitude types: complex64 (float2, the default) or complex128 (double2,
+// the plain method's amp_dtype option); Real<V> is the component type.
+template <class V> struct RealOf;
+template <> struct RealOf<float2> { using T = float; };
+template <> struct RealOf<double2> { using T = double; };
+template <class V> using Real = typename RealOf<V>::T;
+template <class V> struct CplxOf;
+template <> struct CplxOf<float> { using T = float2; };
+template <> struct CplxOf<double> { using T = double2; };
+template <class R> using Cplx = typename CplxOf<R>::T;
 
-__device__ __forceinline__ const float* mat_ptr(const float* mats, int32_t slot, int b,
-                                                int n_shared, int n_ps) {
+__device__ __forceinline__ float2 mkc(float re, float im) { return make_float2(re, im); }
+__device__ __forceinline__ double2 mkc(double re, double im) { return make_double2(re, im); }
+
+template <class V> struct M2T { V m00, m01, m10, m11; };
+using M2 = M2T<float2>;
+
+template <class R>
+__device__ __forceinline__ const R* mat_ptr(const R* mats, int32_t slot, int b, int n_shared, int n_ps) {
     return slot >= 0 ? mats + 8 * (size_t)slot
                      : mats + 8 * ((size_t)n_shared + (size_t)b * n_ps + (size_t)(-slot - 1));
 }
 
-__device__ __forceinline__ M2 load_m2(const float* p) {
-    M2 m;
-    m.m00 = make_float2(p[0], p[1]);
-    m.m01 = make_float2(p[2], p[3]);
-    m.m10 = make_float2(p[4], p[5]);
-    m.m11 = make_float2(p[6], p[7]);
+template <class R>
+__device__ __forceinline__ M2T<Cplx<R>> load_m2(const R* p) {
+    M2T<Cplx<R>> m;
+    m.m00 = mkc(p[0], p[1]);
+    m.m01 = mkc(p[2], p[3]);
+    m.m10 = mkc(p[4], p[5]);
+    m.m11 = mkc(p[6], p[7]);
     return m;
 }
 
@@ -90,6 +109,8 @@ __device__ __forceinline__ float row_sum(float v) {
 
 __device__ __forceinline__ float im_conj_mul(float2 l, float2 p) { return l.x * p.y - l.y * p.x; }
 __device__ __forceinline__ float re_conj_mul(float2 l, float2 p) { return l.x * p.x + l.y * p.y; }
+__device__ __forceinline__ double im_conj_mul(double2 l, double2 p) { return l.x * p.y - l.y * p.x; }
+__device__ __forceinline__ double re_conj_mul(double2 l, double2 p) { return l.x * p.x + l.y * p.y; }
 
 // Bank-conflict swizzle of a tile-local amplitude index (bijection on [0, 2^m)).
 __device__ __forceinline__ int swz(int l) { return l ^ (((l >> 5) ^ (l >> 10)) & 31); }
@@ -102,18 +123,19 @@ __device__ __forceinline__ int64_t insert_bit(int64_t x, int s, int v) {
 // ----------------------------------------------------------------------------
 // gate-matrix cache evaluation
 // ----------------------------------------------------------------------------
+template <class R>  // R: matrix entry type (float, or double for complex128 states)
 __global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restrict__ recipes,
                        const int32_t* __restrict__ rg, int n_recipes,
                        const float* __restrict__ weights, const float* __restrict__ inputs,
-                       int n_inputs, int n_shared, int n_ps, int remap, float* __restrict__ mats) {
+                       int n_inputs, int n_shared, int n_ps, int remap, R* __restrict__ mats) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (r >= n_recipes) return;
-    const DRecipe R = recipes[r];
-    if (R.out >= 0 && b != 0) return;
+    const DRecipe Rc = recipes[r];
+    if (Rc.out >= 0 && b != 0) return;
     double M[8] = {1, 0, 0, 0, 0, 0, 1, 0};
-    for (int i = 0; i < R.count; ++i) {
-        const DGate& G = gates[rg[R.first + i]];
+    for (int i = 0; i < Rc.count; ++i) {
+        const DGate& G = gates[rg[Rc.first + i]];
         double th = 0.0;
         if (G.src == QSV_SRC_WEIGHT) {
             th = (double)weights[G.idx];
@@ -140,17 +162,17 @@ __global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restric
             }
         for (int e = 0; e < 8; ++e) M[e] = N[e];
     }
-    float out[8];
-    if (R.dagger) {
-        out[0] = (float)M[0]; out[1] = (float)-M[1];  // m00*
-        out[2] = (float)M[4]; out[3] = (float)-M[5];  // m10*
-        out[4] = (float)M[2]; out[5] = (float)-M[3];  // m01*
-        out[6] = (float)M[6]; out[7] = (float)-M[7];  // m11*
+    R out[8];
+    if (Rc.dagger) {
+        out[0] = (R)M[0]; out[1] = (R)-M[1];  // m00*
+        out[2] = (R)M[4]; out[3] = (R)-M[5];  // m10*
+        out[4] = (R)M[2]; out[5] = (R)-M[3];  // m01*
+        out[6] = (R)M[6]; out[7] = (R)-M[7];  // m11*
     } else {
-        for (int e = 0; e < 8; ++e) out[e] = (float)M[e];
+        for (int e = 0; e < 8; ++e) out[e] = (R)M[e];
     }
-    float* dst = R.out >= 0 ? mats + 8 * (size_t)R.out
-                            : mats + 8 * ((size_t)n_shared + (size_t)b * n_ps + (size_t)(-R.out - 1));
+    R* dst = Rc.out >= 0 ? mats + 8 * (size_t)Rc.out
+                         : mats + 8 * ((size_t)n_shared + (size_t)b * n_ps + (size_t)(-Rc.out - 1));
     for (int e = 0; e < 8; ++e) dst[e] = out[e];
 }
 
@@ -159,28 +181,30 @@ __global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restric
 // prefix matrix of qubit q. Work split: chunk of 2^cb amplitudes per block,
 // lanes over the low tb bits, a loop over the next jb bits.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ float2 prefix_v(const float* mats, const int32_t* pm, int q, int bit,
-                                           int b, int n_shared, int n_ps) {
-    const float* M = mat_ptr(mats, pm[q], b, n_shared, n_ps);
-    return bit ? make_float2(M[4], M[5]) : make_float2(M[0], M[1]);
+template <class R>
+__device__ __forceinline__ Cplx<R> prefix_v(const R* mats, const int32_t* pm, int q, int bit,
+                                            int b, int n_shared, int n_ps) {
+    const R* M = mat_ptr(mats, pm[q], b, n_shared, n_ps);
+    return bit ? mkc(M[4], M[5]) : mkc(M[0], M[1]);
 }
 
-__global__ __launch_bounds__(256) void k_init(float2* __restrict__ state, int W,
+template <class V>
+__global__ __launch_bounds__(256) void k_init(V* __restrict__ state, int W,
                                               const int32_t* __restrict__ pm,
-                                              const float* __restrict__ mats, int n_shared,
+                                              const Real<V>* __restrict__ mats, int n_shared,
                                               int n_ps) {
     const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
     const int t = threadIdx.x;
     if (t >= (1 << tb)) return;
     const int b = blockIdx.y;
     const int64_t chunk = blockIdx.x;
-    float2 P = make_float2(1.f, 0.f);
+    V P = mkc(Real<V>(1), Real<V>(0));
     for (int s = 0; s < tb; ++s) P = cmul(P, prefix_v(mats, pm, W - 1 - s, (t >> s) & 1, b, n_shared, n_ps));
     for (int s = cb; s < W; ++s)
         P = cmul(P, prefix_v(mats, pm, W - 1 - s, (int)((chunk >> (s - cb)) & 1), b, n_shared, n_ps));
-    float2* st = state + ((size_t)b << W);
+    V* st = state + ((size_t)b << W);
     for (int j = 0; j < (1 << jb); ++j) {
-        float2 Q = P;
+        V Q = P;
         for (int s = tb; s < cb; ++s)
             Q = cmul(Q, prefix_v(mats, pm, W - 1 - s, (j >> (s - tb)) & 1, b, n_shared, n_ps));
         st[(chunk << cb) | ((int64_t)j << tb) | t] = Q;
@@ -190,20 +214,22 @@ __global__ __launch_bounds__(256) void k_init(float2* __restrict__ state, int W,
 // ----------------------------------------------------------------------------
 // readout
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_expval_part(const float2* __restrict__ state, int W,
+template <class V>
+__global__ __launch_bounds__(256) void k_expval_part(const V* __restrict__ state, int W,
                                                      double* __restrict__ part) {
+    using R = Real<V>;
     __shared__ double red[4][14];
     const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
     const int t = threadIdx.x;
     const int b = blockIdx.y;
     const int64_t chunk = blockIdx.x;
     const int64_t nchunk = gridDim.x;
-    const float2* st = state + ((size_t)b << W);
-    float T = 0.f, S[4] = {0.f, 0.f, 0.f, 0.f};
+    const V* st = state + ((size_t)b << W);
+    R T = 0, S[4] = {0, 0, 0, 0};
     if (t < (1 << tb)) {
         for (int j = 0; j < (1 << jb); ++j) {
-            const float2 a = st[(chunk << cb) | ((int64_t)j << tb) | t];
-            const float p = a.x * a.x + a.y * a.y;
+            const V a = st[(chunk << cb) | ((int64_t)j << tb) | t];
+            const R p = a.x * a.x + a.y * a.y;
             T += p;
             for (int i = 0; i < jb; ++i)
                 if ((j >> i) & 1) S[i] += p;
@@ -313,24 +339,25 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
 // ----------------------------------------------------------------------------
 constexpr int kPgItems = 4;
 
-__device__ __forceinline__ void pair_apply(int cls, const M2& M, float2& x, float2& y) {
-    float2 u, v;
+template <class V>
+__device__ __forceinline__ void pair_apply(int cls, const M2T<V>& M, V& x, V& y) {
+    V u, v;
     switch (cls) {
     case OP_SWAP: u = y; v = x; break;
     case OP_REAL:
-        u = make_float2(M.m00.x * x.x + M.m01.x * y.x, M.m00.x * x.y + M.m01.x * y.y);
-        v = make_float2(M.m10.x * x.x + M.m11.x * y.x, M.m10.x * x.y + M.m11.x * y.y);
+        u = mkc(M.m00.x * x.x + M.m01.x * y.x, M.m00.x * x.y + M.m01.x * y.y);
+        v = mkc(M.m10.x * x.x + M.m11.x * y.x, M.m10.x * x.y + M.m11.x * y.y);
         break;
     case OP_RXL: {
-        const float a = M.m00.x, bb = M.m01.y;
-        u = make_float2(a * x.x - bb * y.y, a * x.y + bb * y.x);
-        v = make_float2(a * y.x - bb * x.y, a * y.y + bb * x.x);
+        const Real<V> a = M.m00.x, bb = M.m01.y;
+        u = mkc(a * x.x - bb * y.y, a * x.y + bb * y.x);
+        v = mkc(a * y.x - bb * x.y, a * y.y + bb * x.x);
         break;
     }
     default: {
-        const float2 p = cmul(M.m00, x), q = cmul(M.m01, y), r = cmul(M.m10, x), s = cmul(M.m11, y);
-        u = make_float2(p.x + q.x, p.y + q.y);
-        v = make_float2(r.x + s.x, r.y + s.y);
+        const V p = cmul(M.m00, x), q = cmul(M.m01, y), r = cmul(M.m10, x), s = cmul(M.m11, y);
+        u = mkc(p.x + q.x, p.y + q.y);
+        v = mkc(r.x + s.x, r.y + s.y);
         break;
     }
     }
@@ -378,8 +405,9 @@ __device__ __forceinline__ bool pg_ctl_ok(const PGate& pg, int64_t idx) {
     return (pg.csh < 0 || ((idx >> pg.csh) & 1)) && (pg.csh2 < 0 || ((idx >> pg.csh2) & 1));
 }
 
-__global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, int W, int64_t B,
-                                                  PGate pg, const float* __restrict__ mats,
+template <class V>
+__global__ __launch_bounds__(256) void k_pg_apply(V* __restrict__ state, int W, int64_t B,
+                                                  PGate pg, const Real<V>* __restrict__ mats,
                                                   int n_shared, int n_ps) {
     // kPgItems items per thread, 256 apart (coalesced). Items touch disjoint
     // amplitudes, so every load of the thread is issued before the first store:
@@ -387,7 +415,7 @@ __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, in
     const int64_t base = ((int64_t)blockIdx.x * kPgItems) * 256 + threadIdx.x;
     if (pg.cls == OP_DIAG) {
         const int64_t total = B << W;
-        float2 a[kPgItems];
+        V a[kPgItems];
 #pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
             const int64_t it = base + i * 256;
@@ -398,14 +426,14 @@ __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, in
             const int64_t it = base + i * 256;
             if (it >= total || !pg_ctl_ok(pg, it)) continue;
             const int b = (int)(it >> W);
-            const M2 M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
-            const float2 ph = ((it >> pg.tsh) & 1) ? M.m11 : M.m00;
+            const auto M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
+            const V ph = ((it >> pg.tsh) & 1) ? M.m11 : M.m00;
             state[it] = cmul(ph, a[i]);
         }
     } else if (pg.cls == OP_SIGN) {
         const PgBits f = pg_bits(pg);
         const int64_t total = B << (W - f.n);
-        float2 a[kPgItems];
+        V a[kPgItems];
         int64_t idx[kPgItems];
 #pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
@@ -415,12 +443,12 @@ __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, in
         }
 #pragma unroll
         for (int i = 0; i < kPgItems; ++i)
-            if (idx[i] >= 0) state[idx[i]] = make_float2(-a[i].x, -a[i].y);
+            if (idx[i] >= 0) state[idx[i]] = mkc(-a[i].x, -a[i].y);
     } else {
         const PgBits f = pg_bits(pg);
         const int64_t total = B << (W - f.n);
         const int64_t step = int64_t(1) << pg.tsh;
-        float2 x[kPgItems], y[kPgItems];
+        V x[kPgItems], y[kPgItems];
         int64_t i0[kPgItems];
 #pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
@@ -434,7 +462,7 @@ __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, in
 #pragma unroll
         for (int i = 0; i < kPgItems; ++i) {
             if (i0[i] < 0) continue;
-            M2 M{};
+            M2T<V> M{};
             if (pg.cls != OP_SWAP) M = load_m2(mat_ptr(mats, pg.mat, (int)(i0[i] >> W), n_shared, n_ps));
             pair_apply(pg.cls, M, x[i], y[i]);
             state[i0[i]] = x[i];
@@ -444,8 +472,9 @@ __global__ __launch_bounds__(256) void k_pg_apply(float2* __restrict__ state, in
 }
 
 // lambda = D psi_N with D(idx) = sum_i g[b,i] (1 - 2 bit_i(idx)); psi copied to the workspace.
-__global__ __launch_bounds__(256) void k_adj_init(const float2* __restrict__ psiN,
-                                                  float2* __restrict__ psi, float2* __restrict__ lam,
+template <class V>
+__global__ __launch_bounds__(256) void k_adj_init(const V* __restrict__ psiN,
+                                                  V* __restrict__ psi, V* __restrict__ lam,
                                                   int W, int64_t B, const double* __restrict__ g) {
     const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (it >= (B << W)) return;
@@ -456,26 +485,27 @@ __global__ __launch_bounds__(256) void k_adj_init(const float2* __restrict__ psi
         const double gi = g[b * W + i];
         d += ((idx >> (W - 1 - i)) & 1) ? -gi : gi;
     }
-    const float2 a = psiN[it];
+    const V a = psiN[it];
     psi[it] = a;
-    lam[it] = make_float2((float)d * a.x, (float)d * a.y);
+    lam[it] = mkc((Real<V>)d * a.x, (Real<V>)d * a.y);
 }
 
 // Plain-method backward step for one gate: gradient partial at psi_k, lambda_k,
 // then psi <- U^dagger psi, lambda <- U^dagger lambda. Grid (nch, B).
-__global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2* __restrict__ lam,
+template <class V>
+__global__ __launch_bounds__(256) void k_pg_adj(V* __restrict__ psi, V* __restrict__ lam,
                                                 int W, int B, PGate pg,
-                                                const float* __restrict__ mats, int n_shared,
+                                                const Real<V>* __restrict__ mats, int n_shared,
                                                 int n_ps, double* __restrict__ part, int64_t nch) {
     __shared__ double red[4];
     const int t = threadIdx.x;
     const int b = blockIdx.y;
     const int64_t chunk = blockIdx.x;
     const size_t off = (size_t)b << W;
-    float2* P = psi + off;
-    float2* L = lam + off;
-    float acc = 0.f;
-    M2 M{};
+    V* P = psi + off;
+    V* L = lam + off;
+    Real<V> acc = 0;
+    M2T<V> M{};
     if (pg.cls != OP_SWAP && pg.cls != OP_SIGN) M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
     if (pg.cls == OP_DIAG) {
         const int64_t n = int64_t(1) << W, per = n / nch;
@@ -483,9 +513,9 @@ __global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2
             const int64_t idx = chunk * per + e;
             if (!pg_ctl_ok(pg, idx)) continue;
             const int bit = (idx >> pg.tsh) & 1;
-            float2 p = P[idx], l = L[idx];
+            V p = P[idx], l = L[idx];
             if (pg.grad == OP_GZ) acc += bit ? -im_conj_mul(l, p) : im_conj_mul(l, p);
-            const float2 ph = bit ? M.m11 : M.m00;
+            const V ph = bit ? M.m11 : M.m00;
             P[idx] = cmul(ph, p);
             L[idx] = cmul(ph, l);
         }
@@ -494,9 +524,9 @@ __global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2
         const int64_t n = int64_t(1) << (W - f.n), per = n / nch;
         for (int64_t e = t; e < per; e += 256) {
             const int64_t idx = pg_index(chunk * per + e, f);
-            const float2 p = P[idx], l = L[idx];
-            P[idx] = make_float2(-p.x, -p.y);
-            L[idx] = make_float2(-l.x, -l.y);
+            const V p = P[idx], l = L[idx];
+            P[idx] = mkc(-p.x, -p.y);
+            L[idx] = mkc(-l.x, -l.y);
         }
     } else {
         const PgBits f = pg_bits(pg);
@@ -505,7 +535,7 @@ __global__ __launch_bounds__(256) void k_pg_adj(float2* __restrict__ psi, float2
             const int64_t it = chunk * per + e;
             const int64_t i0 = pg_index(it, f);
             const int64_t i1 = i0 | (int64_t(1) << pg.tsh);
-            float2 p0 = P[i0], p1 = P[i1], l0 = L[i0], l1 = L[i1];
+            V p0 = P[i0], p1 = P[i1], l0 = L[i0], l1 = L[i1];
             if (pg.grad == OP_GX) acc += im_conj_mul(l0, p1) + im_conj_mul(l1, p0);
             else if (pg.grad == OP_GY) acc += re_conj_mul(l1, p0) - re_conj_mul(l0, p1);
             pair_apply(pg.cls, M, p0, p1);
@@ -1415,8 +1445,12 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     return QSV_OK;
 }
 
+// complex128 amplitudes (and float64 gate matrices) for the plain method's amp_dtype = 1
+bool c128(const qsv_plan_t* p) { return p->opts.amp_dtype == QSV_AMP_C128; }
+size_t amp_size(const qsv_plan_t* p) { return c128(p) ? 16 : 8; }
+
 size_t mats_bytes(const qsv_plan_t* p, int64_t B) {
-    return align256(((size_t)p->n_shared_mats + (size_t)B * p->n_ps_mats) * 8 * sizeof(float) + 32);
+    return align256(((size_t)p->n_shared_mats + (size_t)B * p->n_ps_mats) * 8 * (amp_size(p) / 2) + 32);
 }
 
 int64_t grad_nch(const qsv_plan_t* p) {
@@ -1429,7 +1463,7 @@ int64_t expval_nchunk(const qsv_plan_t* p) { return int64_t(1) << (p->W - std::m
 // amplitudes of one sample (all circuits of a multi-circuit plan)
 int64_t row_amps(const qsv_plan_t* p) { return p->multi ? p->row : int64_t(1) << p->W; }
 
-size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * (size_t)row_amps(p) * 8; }
+size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * (size_t)row_amps(p) * amp_size(p); }
 
 size_t partial_bytes(const qsv_plan_t* p, int64_t B) {
     return align256((size_t)std::max<int64_t>(p->pu_total, 1) * B * sizeof(double));
@@ -1451,9 +1485,15 @@ int run_coef(const qsv_plan_t* p, DeviceTables* T, const float* w, const float* 
     if (nr == 0) return QSV_OK;
     dim3 grid((nr + 127) / 128, (unsigned)(p->n_ps_mats ? B : 1));
     hipEvent_t ev = prof_begin(p, s);
-    hipLaunchKernelGGL(k_coef, grid, dim3(128), 0, s, T->gates, T->recipes, T->recipe_gates, nr,
-                       w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, (int)p->opts.weight_remap, mats);
-    prof_end(p, s, ev, K_COEF, 32.0 * ((double)p->n_shared_mats + (double)B * p->n_ps_mats), 0.0);
+    if (c128(p))
+        hipLaunchKernelGGL(k_coef<double>, grid, dim3(128), 0, s, T->gates, T->recipes, T->recipe_gates, nr,
+                           w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, (int)p->opts.weight_remap,
+                           (double*)mats);
+    else
+        hipLaunchKernelGGL(k_coef<float>, grid, dim3(128), 0, s, T->gates, T->recipes, T->recipe_gates, nr,
+                           w, x, p->n_inputs, p->n_shared_mats, p->n_ps_mats, (int)p->opts.weight_remap, mats);
+    prof_end(p, s, ev, K_COEF, 4.0 * (double)amp_size(p) * ((double)p->n_shared_mats + (double)B * p->n_ps_mats),
+             0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }
@@ -1463,10 +1503,14 @@ int run_init(const qsv_plan_t* p, DeviceTables* T, const float* mats, int64_t B,
     const int cb = std::min(p->W, 12);
     dim3 grid((unsigned)(int64_t(1) << (p->W - cb)), (unsigned)B);
     hipEvent_t ev = prof_begin(p, s);
-    hipLaunchKernelGGL(k_init, grid, dim3(256), 0, s, st, p->W, T->prefix_mat, mats,
-                       p->n_shared_mats, p->n_ps_mats);
+    if (c128(p))
+        hipLaunchKernelGGL(k_init<double2>, grid, dim3(256), 0, s, (double2*)st, p->W, T->prefix_mat,
+                           (const double*)mats, p->n_shared_mats, p->n_ps_mats);
+    else
+        hipLaunchKernelGGL(k_init<float2>, grid, dim3(256), 0, s, st, p->W, T->prefix_mat, mats,
+                           p->n_shared_mats, p->n_ps_mats);
     const double amps = (double)B * (double)(int64_t(1) << p->W);
-    prof_end(p, s, ev, K_INIT, 8.0 * amps, 0.0);
+    prof_end(p, s, ev, K_INIT, (double)amp_size(p) * amps, 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }
@@ -1644,6 +1688,11 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.amp_dtype != QSV_AMP_C64 && o.amp_dtype != QSV_AMP_C128) { set_error("amp_dtype must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.amp_dtype == QSV_AMP_C128 && o.method != QSV_METHOD_PER_GATE) {
+        set_error("complex128 amplitudes (amp_dtype = 1) need method = per_gate");
+        return QSV_ERR_ARG;
+    }
     for (int g = 0; g < n_gates; ++g) {
         const qsv_gate& G = gates[g];
         char buf[160];
@@ -1852,9 +1901,13 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
             else items = B << (W - nfix);
             const int64_t blocks = (items + 256 * kPgItems - 1) / (256 * kPgItems);
             hipEvent_t ev = prof_begin(p, s);
-            hipLaunchKernelGGL(k_pg_apply, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
-                               (const float*)mats, p->n_shared_mats, p->n_ps_mats);
-            prof_end(p, s, ev, K_PG_APPLY, 16.0 * touched * amps, p->pg_fwd_flops[i] * amps,
+            if (c128(p))
+                hipLaunchKernelGGL(k_pg_apply<double2>, dim3((unsigned)blocks), dim3(256), 0, s, (double2*)st, W,
+                                   B, pg, (const double*)mats, p->n_shared_mats, p->n_ps_mats);
+            else
+                hipLaunchKernelGGL(k_pg_apply<float2>, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
+                                   (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+            prof_end(p, s, ev, K_PG_APPLY, 2.0 * (double)amp_size(p) * touched * amps, p->pg_fwd_flops[i] * amps,
                      kPgSub0 + pg_prof_class(pg));
         }
         HIP_TRY(hipGetLastError());
@@ -1964,9 +2017,13 @@ int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out,
     double* part = (double*)ws;
     const double amps = (double)B * (double)(int64_t(1) << p->W);
     hipEvent_t ev = prof_begin(p, s);
-    hipLaunchKernelGGL(k_expval_part, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
-                       (const float2*)d_state, p->W, part);
-    prof_end(p, s, ev, K_EXPVAL_PART, 8.0 * amps, 3.0 * amps);
+    if (c128(p))
+        hipLaunchKernelGGL(k_expval_part<double2>, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
+                           (const double2*)d_state, p->W, part);
+    else
+        hipLaunchKernelGGL(k_expval_part<float2>, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
+                           (const float2*)d_state, p->W, part);
+    prof_end(p, s, ev, K_EXPVAL_PART, (double)amp_size(p) * amps, 3.0 * amps);
     ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_expval_final, dim3((unsigned)p->W, (unsigned)B), dim3(256), 0, s,
                        (const double*)part, p->W, nchunk, out);
@@ -2028,17 +2085,26 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     } else if (p->opts.method == QSV_METHOD_PER_GATE) {
         const int64_t n = B << W;
         hipEvent_t ev = prof_begin(p, s);
-        hipLaunchKernelGGL(k_adj_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           (const float2*)d_state, psi, lam, W, B, gout);
-        prof_end(p, s, ev, K_ADJ_INIT, 24.0 * amps, 2.0 * W * amps);
+        if (c128(p))
+            hipLaunchKernelGGL(k_adj_init<double2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                               (const double2*)d_state, (double2*)psi, (double2*)lam, W, B, gout);
+        else
+            hipLaunchKernelGGL(k_adj_init<float2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                               (const float2*)d_state, psi, lam, W, B, gout);
+        prof_end(p, s, ev, K_ADJ_INIT, 3.0 * (double)amp_size(p) * amps, 2.0 * W * amps);
         for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
             const PGate& pg = p->pg_bwd[i];
             const double touched = pg_touched(pg);
             ev = prof_begin(p, s);
-            hipLaunchKernelGGL(k_pg_adj, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi,
-                               lam, W, (int)B, pg, (const float*)mats, p->n_shared_mats,
-                               p->n_ps_mats, part, nch);
-            prof_end(p, s, ev, K_PG_ADJ, 32.0 * touched * amps, p->pg_bwd_flops[i] * amps,
+            if (c128(p))
+                hipLaunchKernelGGL(k_pg_adj<double2>, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s,
+                                   (double2*)psi, (double2*)lam, W, (int)B, pg, (const double*)mats,
+                                   p->n_shared_mats, p->n_ps_mats, part, nch);
+            else
+                hipLaunchKernelGGL(k_pg_adj<float2>, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi,
+                                   lam, W, (int)B, pg, (const float*)mats, p->n_shared_mats,
+                                   p->n_ps_mats, part, nch);
+            prof_end(p, s, ev, K_PG_ADJ, 4.0 * (double)amp_size(p) * touched * amps, p->pg_bwd_flops[i] * amps,
                      kPgSub0 + pg_prof_class(pg));
         }
     } else {
@@ -2099,6 +2165,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.amp_dtype != QSV_AMP_C64) { set_error("multi-circuit plans use complex64 amplitudes (amp_dtype = 0)"); return QSV_ERR_ARG; }
     std::vector<CircuitIn> cs;
     int64_t row = 0;
     for (int c = 0; c < n_circuits; ++c) {
@@ -2271,18 +2338,19 @@ int qsv_plan_estimate(const qsv_plan_t* p, int64_t B, double hbm_gbs, double alu
         launches += nf + nb + 2;
     } else {
         const double a = (double)B * (double)(int64_t(1) << p->W);
-        t += 2.0 * sweep(8.0 * a, 0.0);  // init + readout
+        const double e = (double)amp_size(p);  // bytes per amplitude
+        t += 2.0 * sweep(e * a, 0.0);  // init + readout
         if (p->opts.method == QSV_METHOD_PER_GATE) {
-            t += sweep(24.0 * a, 0.0);  // adjoint init
+            t += sweep(3.0 * e * a, 0.0);  // adjoint init
             for (size_t i = 0; i < p->pg_fwd.size(); ++i) {
                 const PGate& g = p->pg_fwd[i];
                 const double touched = pg_touched(g);
-                t += sweep(16.0 * touched * a, p->pg_fwd_flops[i] * a);
+                t += sweep(2.0 * e * touched * a, p->pg_fwd_flops[i] * a);
             }
             for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
                 const PGate& g = p->pg_bwd[i];
                 const double touched = pg_touched(g);
-                t += sweep(32.0 * touched * a, p->pg_bwd_flops[i] * a);
+                t += sweep(4.0 * e * touched * a, p->pg_bwd_flops[i] * a);
             }
             launches += (int64_t)(p->pg_fwd.size() + p->pg_bwd.size()) + 2;
         } else {

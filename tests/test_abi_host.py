@@ -80,6 +80,28 @@ def test_plan_rejects_bad_options(lib):
         assert _plan_rc(4, [(0, 0, -1, 0, -1)], opts=o) == -1, field
 
 
+def test_c128_amplitudes_only_with_the_plain_method(lib):
+    c = I.rx_ry_rz_cz_ladder(6, 2)
+    o = B.qsv_default_opts()
+    o.amp_dtype = 2
+    o.method = 1
+    assert _plan_rc(4, [(0, 0, -1, 0, -1)], opts=o) == -1
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="fused", amp_dtype="c128")
+    assert e.value.code == -1 and "per_gate" in str(e.value)
+    with pytest.raises(B.QsvError):
+        B.MultiPlan([I.rx_ry_rz_cz_ladder(5, 1), I.rx_ry_rz_cz_ladder(6, 1)], amp_dtype="c128")
+    p64 = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="per_gate")
+    p128 = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="per_gate", amp_dtype="c128")
+    batch, S = 8, 8 * (1 << c.n_qubits)  # S: complex64 bytes of the batch
+    # backward workspace: matrices, then psi and lambda copies (twice the bytes), then partials
+    d = B.qsv_workspace_size(p128.handle, batch, 2) - B.qsv_workspace_size(p64.handle, batch, 2)
+    assert d >= 2 * batch * S
+    assert B.qsv_workspace_size(p128.handle, batch, 0) > B.qsv_workspace_size(p64.handle, batch, 0)
+    # readout partials are float64 either way
+    assert B.qsv_workspace_size(p128.handle, batch, 1) == B.qsv_workspace_size(p64.handle, batch, 1)
+
+
 def test_calls_validate_before_touching_the_device(lib):
     c = I.rx_ry_rz_cz_ladder(5, 1)
     h = B.qsv_plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs)

@@ -267,3 +267,35 @@ def test_dag_splitter(orc, method, k):
               I.random_mixed(10, 150, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS),
               I.rx_ry_rz_cz_ladder(14, 3)):
         _check(c, 2, 200 + k, orc, method, fuse_width=k, splitter=1)
+
+
+C128_TOL = 1e-12   # max-abs on amplitudes and <Z_i> with complex128 amplitudes
+C128_GRAD = 1e-10  # relative on gradients
+
+
+@pytest.mark.parametrize("case", ["w6_b8_ring", "mixed_all_kinds_w7", "mixed_inputs_w9"])
+def test_c128_plain_method(orc, case):
+    """The plain method instantiated for complex128 amplitudes and float64 gate
+    matrices (the oracle's own precision): amplitudes and <Z_i> within 1e-12
+    of the complex128 oracle, gradients within 1e-10 relative."""
+    rng = np.random.default_rng(91)
+    if case == "w6_b8_ring":
+        c, batch, seed = I.workload("w6_b8_ring")
+    elif case == "mixed_all_kinds_w7":
+        c, batch, seed = I.random_mixed(7, 120, rng, kinds=I.ALL_KINDS), 3, 92
+    else:
+        c, batch, seed = I.random_mixed(9, 150, rng, n_inputs=4, p_input=0.3), 5, 93
+    w, x = I.draw_angles(c, batch, seed)
+    g = I.draw_grad_out(c, batch, seed)
+    print(f"[parity] c128 {case} B={batch}", flush=True)
+    got = gpu_run(c, w, x, batch, g, method="per_gate", amp_dtype="c128")
+    assert got["state"].dtype == torch.complex128
+    ref = oracle_run(orc, c, w, x, batch, g)
+    assert np.abs(got["state"].cpu().numpy() - ref["state"]).max() <= C128_TOL
+    assert np.abs(got["E"].cpu().numpy() - ref["E"]).max() <= C128_TOL
+    assert np.abs(got["E_fused"].cpu().numpy() - ref["E"]).max() <= C128_TOL
+    ok, rel = grad_close(got["gw"].cpu().numpy(), ref["gw"], tol=C128_GRAD)
+    assert ok, ("weights", rel)
+    if c.n_inputs:
+        ok, rel = grad_close(got["gx"].cpu().numpy(), ref["gx"], tol=C128_GRAD)
+        assert ok, ("inputs", rel)
