@@ -124,7 +124,7 @@ def log(args, *a):
 
 
 def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
-    """Warm up, then time `steps` steps; returns (ms_per_step, per-kernel stats, all ms)."""
+    """Warm up, then time `steps` steps; returns (ms_per_step, per-kernel stats, per-step ms)."""
     B = state.shape[0]
     n = len(ws_inputs)
 
@@ -139,18 +139,25 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
     plan.profile(True)
     plan.profile_read()  # drop anything recorded before the timed region
     stream = torch.cuda.current_stream()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    t0.record(stream)
-    for r in range(warmup, warmup + steps):
+    ev[0].record(stream)
+    for i, r in enumerate(range(warmup, warmup + steps)):
         step(r)
-    t1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
+    total_ms = ev[0].elapsed_time(ev[-1])
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     stats = plan.profile_read()
     plan.profile(False)
-    return total_ms / steps, stats
+    return total_ms / steps, stats, step_ms
+
+
+def step_spread(ms_list):
+    """Mean, min and standard deviation of per-step times (ms)."""
+    import statistics
+    return {"mean": round(statistics.fmean(ms_list), 4), "min": round(min(ms_list), 4),
+            "std": round(statistics.pstdev(ms_list), 4) if len(ms_list) > 1 else 0.0}
 
 
 def bench_uneven(args, torch, dev, binding, inputs):
@@ -185,7 +192,7 @@ def bench_uneven(args, torch, dev, binding, inputs):
 
     # eager, profiled: algorithmic bytes per step and the per-kernel split
     eager = [(w, xbuf) for w in runs]
-    ems, stats = run_steps(plan, eager, g, state, E, gw, gx, args.uneven_steps, args.warmup, torch)
+    ems, stats, _ = run_steps(plan, eager, g, state, E, gw, gx, args.uneven_steps, args.warmup, torch)
     step_bytes = sum(v["bytes"] for v in stats.values()) / args.uneven_steps
 
     torch.cuda.synchronize()
@@ -266,7 +273,8 @@ def main():
     gw = torch.empty((max(circ.n_weights, 1),), dtype=torch.float64, device=dev)
     gx = torch.empty((B, max(circ.n_inputs, 1)), dtype=torch.float64, device=dev)
 
-    ms, stats = run_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch)
+    ms, stats, step_ms = run_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch)
+    spread = step_spread(step_ms)
     log(args, f"[bench] fused: {ms:.3f} ms/step")
     fam = families(stats)
     for k, v in sorted(list(fam.items()) + [kv for kv in stats.items() if family(kv[0]) != kv[0]],
@@ -288,7 +296,7 @@ def main():
     # plain per-gate method on the same inputs
     pg = None
     if args.per_gate_steps > 0:
-        pms, pstats = run_steps(per_gate, runs, g, state, E, gw, gx, args.per_gate_steps, 1, torch)
+        pms, pstats, _ = run_steps(per_gate, runs, g, state, E, gw, gx, args.per_gate_steps, 1, torch)
         pbytes = sum(v["bytes"] for v in pstats.values()) / args.per_gate_steps
         copy_gbs = copy_rate()["gbs"]
         pg = {"ms_per_step": round(pms, 3), "evals_per_s": round(B / (pms / 1e3), 2),
@@ -356,6 +364,7 @@ def main():
         "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3),
+        "step_ms": spread,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic: seeded inputs x~U(-pi,pi), weights~U(0,2pi), fresh per step",
