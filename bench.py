@@ -237,7 +237,7 @@ def main():
         copy_calibration(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "libqsv runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
