@@ -275,6 +275,7 @@ def main():
 
     ms, stats, step_ms = run_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch)
     spread = step_spread(step_ms)
+    copy_gbs = copy_rate()["gbs"]  # on-box reference rate for HBM-bound kernels
     log(args, f"[bench] fused: {ms:.3f} ms/step")
     fam = families(stats)
     for k, v in sorted(list(fam.items()) + [kv for kv in stats.items() if family(kv[0]) != kv[0]],
@@ -298,7 +299,6 @@ def main():
     if args.per_gate_steps > 0:
         pms, pstats, _ = run_steps(per_gate, runs, g, state, E, gw, gx, args.per_gate_steps, 1, torch)
         pbytes = sum(v["bytes"] for v in pstats.values()) / args.per_gate_steps
-        copy_gbs = copy_rate()["gbs"]
         pg = {"ms_per_step": round(pms, 3), "evals_per_s": round(B / (pms / 1e3), 2),
               "hbm_gbs": round(pbytes / (pms / 1e3) / 1e9, 1),
               "hbm_frac": round(pbytes / (pms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -376,8 +376,13 @@ def main():
                    "plan_ms": round(plan_ms, 2)},
         "per_gate": pg,
         "speedup_fused_vs_per_gate": round(pg["ms_per_step"] / ms, 2) if pg else None,
+        # per kernel (and per family of generated pass kernels): algorithmic GB/s,
+        # as a fraction of the 8 TB/s peak and of the 1 GiB copy timed in this run
+        "copy_gbs": copy_gbs,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
-                        "gbs": round(v["bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1)}
+                        "gbs": round(v["bytes"] / max(v["total_ms"], 1e-9) / 1e6, 1),
+                        "hbm_frac": round(v["bytes"] / max(v["total_ms"], 1e-9) / 1e6 / HBM_PEAK_GBS, 4),
+                        "copy_frac": round(v["bytes"] / max(v["total_ms"], 1e-9) / 1e6 / copy_gbs, 4)}
                     for k, v in list(fam.items()) + [kv for kv in stats.items()
                                                      if family(kv[0]) != kv[0]]},
         "roofline": roof,

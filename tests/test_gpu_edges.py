@@ -141,3 +141,26 @@ def test_30_qubits_closed_form(method):
     assert np.abs(st - amps).max() <= AMP_TOL
     del got
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", ["fused", "per_gate"])
+def test_ghz_28(method):
+    """GHZ_28 (2 GiB state): exactly two non-zero amplitudes 1/sqrt(2) at
+    |0...0> and |1...1>, and <Z_i> = 0; checked on the device."""
+    import torch
+    W = 28
+    print(f"[edges] GHZ_28 {method}", flush=True)
+    c = I.Circuit(W, name="ghz28")
+    c.fixed("H", 0)
+    for q in range(W - 1):
+        c.fixed("CNOT", q, q + 1)
+    got = gpu_run(c, np.zeros(0, np.float32), np.zeros((1, 0), np.float32), 1, **METHODS[method])
+    st = got["state"][0]
+    r = 1 / math.sqrt(2)
+    ends = st[[0, (1 << W) - 1]].cpu().numpy()
+    assert np.abs(ends - r).max() < AMP_TOL
+    assert st[1:-1].abs().max().item() < 1e-7
+    assert np.abs(got["E"].cpu().numpy()).max() < EXP_TOL
+    del got, st
+    torch.cuda.empty_cache()
