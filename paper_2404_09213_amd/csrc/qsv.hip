@@ -783,39 +783,59 @@ __device__ __forceinline__ int ctl_mask(int ctl, int gT) {
     default: CALL(3); break;        \
     }
 
-// Apply one non-gradient op to one register set.
-__device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], const M2& M, int gT,
-                                         const DTerm* __restrict__ terms) {
+// Apply one non-gradient op to one register set (NA = 1) or to two (NA = 2,
+// psi and lambda in the backward: one dispatch for both).
+template <int NA>
+__device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], float2 (&a2)[kRegs], const M2& M,
+                                         int gT, const DTerm* __restrict__ terms) {
     const bool ctl = op.ctl >= 0;
     const int cm = ctl_mask(op.ctl, gT) & ctl_mask(op.ctl2, gT);
+#define BOTH_(f) \
+    do {                  \
+        f(a);             \
+        if (NA == 2) f(a2); \
+    } while (0)
     switch (op.kind) {
     case OP_U2:
-#define C_(P) if (ctl) r_u2<P, true>(a, M, cm); else r_u2<P, false>(a, M, cm)
+#define U_(x) if (ctl) r_u2<P_, true>(x, M, cm); else r_u2<P_, false>(x, M, cm)
+#define C_(P) { constexpr int P_ = P; BOTH_(U_); }
         QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
+#undef U_
         break;
     case OP_REAL:
-#define C_(P) if (ctl) r_real<P, true>(a, M, cm); else r_real<P, false>(a, M, cm)
+#define U_(x) if (ctl) r_real<P_, true>(x, M, cm); else r_real<P_, false>(x, M, cm)
+#define C_(P) { constexpr int P_ = P; BOTH_(U_); }
         QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
+#undef U_
         break;
     case OP_RXL:
-#define C_(P) if (ctl) r_rxl<P, true>(a, M, cm); else r_rxl<P, false>(a, M, cm)
+#define U_(x) if (ctl) r_rxl<P_, true>(x, M, cm); else r_rxl<P_, false>(x, M, cm)
+#define C_(P) { constexpr int P_ = P; BOTH_(U_); }
         QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
+#undef U_
         break;
     case OP_SWAP:
-#define C_(P) if (ctl) r_swap<P, true>(a, cm); else r_swap<P, false>(a, cm)
+#define U_(x) if (ctl) r_swap<P_, true>(x, cm); else r_swap<P_, false>(x, cm)
+#define C_(P) { constexpr int P_ = P; BOTH_(U_); }
         QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
+#undef U_
         break;
     case OP_DIAG:
         if (op.pos >= 0) {
-#define C_(P) r_diag<P>(a, M, cm)
+#define U_(x) r_diag<P_>(x, M, cm)
+#define C_(P) { constexpr int P_ = P; BOTH_(U_); }
             QSV_DISPATCH_POS(op.pos, C_)
 #undef C_
+#undef U_
         } else {
-            r_phase_all(a, ((gT >> op.sh) & 1) ? M.m11 : M.m00, cm);
+            const float2 ph = ((gT >> op.sh) & 1) ? M.m11 : M.m00;
+#define U_(x) r_phase_all(x, ph, cm)
+            BOTH_(U_);
+#undef U_
         }
         break;
     case OP_SIGN: {
@@ -826,11 +846,14 @@ __device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], cons
                             (tm.s2 < 0 || ((gT >> tm.s2) & 1));
             if (on) flip ^= tm.mask;
         }
-        r_flip(a, flip);
+#define U_(x) r_flip(x, flip)
+        BOTH_(U_);
+#undef U_
         break;
     }
     default: break;
     }
+#undef BOTH_
 }
 
 __device__ __forceinline__ float grad_op(const DOp& op, const float2 (&ps)[kRegs],
@@ -923,7 +946,7 @@ __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
                     nop = O[oi + 1];
                     nM = op_matrix(nop, mats, b, n_shared, n_ps);
                 }
-                apply_op(op, a, M, L.gT, Tm);
+                apply_op<1>(op, a, a, M, L.gT, Tm);
                 op = nop;
                 M = nM;
             }
@@ -1059,8 +1082,7 @@ __device__ __forceinline__ void pass_bwd_tile(
                     // every lane of a row stores the row's sum (same value, same address)
                     red[(wave * 4 + (lane >> 4)) * ng + op.slot] = row_sum(grad_op(op, ps, lm, L.gT));
                 } else {
-                    apply_op(op, ps, M, L.gT, Tm);
-                    apply_op(op, lm, M, L.gT, Tm);
+                    apply_op<2>(op, ps, lm, M, L.gT, Tm);
                 }
                 op = nop;
                 M = nM;
