@@ -790,10 +790,12 @@ __device__ __forceinline__ void apply_op(const DOp& op, float2 (&a)[kRegs], floa
                                          int gT, const DTerm* __restrict__ terms) {
     const bool ctl = op.ctl >= 0;
     const int cm = ctl_mask(op.ctl, gT) & ctl_mask(op.ctl2, gT);
-#define BOTH_(f) \
-    do {                  \
-        f(a);             \
-        if (NA == 2) f(a2); \
+#define BOTH_(f)        \
+    do {                \
+        { f(a); }       \
+        if (NA == 2) {  \
+            f(a2);      \
+        }               \
     } while (0)
     switch (op.kind) {
     case OP_U2:
