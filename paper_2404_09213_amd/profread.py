@@ -29,8 +29,12 @@ def _one(d, suffix):
 
 
 def short(name):
-    """Kernel name without its argument list."""
-    return name.split("(")[0].strip()
+    """Kernel name without its argument list, return type and vector-type
+    spelling: 'void k_pg_adj<HIP_vector_type<float, 2u> >(...)' -> 'k_pg_adj<float2>'."""
+    n = name.split("(")[0].strip()
+    if n.startswith("void "):
+        n = n[5:]
+    return re.sub(r"HIP_vector_type<(\w+), (\d)u>\s*", r"\1\2", n).replace("> >", ">>").replace(" >", ">")
 
 
 def kernel_stats(d):
