@@ -471,6 +471,92 @@ __global__ __launch_bounds__(256) void k_pg_apply(V* __restrict__ state, int W, 
     }
 }
 
+// 16-byte access modes of a complex64 per-gate launch (chosen on the host):
+//  PG_VEC_PAIRS  every index bit the gate fixes is above bit 0, so item i covers
+//                the gate's items 2i and 2i+1, whose amplitudes sit next to each
+//                other (for a pair update: both first and both second amplitudes);
+//                a diagonal gate's items are simply consecutive amplitudes;
+//  PG_VEC_ADJ    the target is bit 0: a pair's two amplitudes are adjacent.
+// Every other launch (a control on bit 0, complex128, a state not 16-byte
+// aligned) takes the scalar kernel. Loads and stores are non-temporal: every
+// amplitude is touched once per launch.
+//  PG_VEC_SWEEP  a sign gate whose lowest fixed bit is 0, 1 or 2: its touched
+//                amplitudes come in runs shorter than a cache line, so every line
+//                moves anyway; all adjacent pairs are read, the amplitudes whose
+//                fixed bits are all 1 negated, and everything written back with
+//                full 16-byte stores.
+enum { PG_SCALAR = 0, PG_VEC_PAIRS = 1, PG_VEC_ADJ = 2, PG_VEC_SWEEP = 3 };
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4v ntl4(const float2* p) { return __builtin_nontemporal_load((const f4v*)p); }
+// cached load: for a pair whose two halves share a cache line (target bit <= 3),
+// where a streaming load of the second half would fetch the line again
+__device__ __forceinline__ f4v ld4(const float2* p, bool cached) {
+    return cached ? *(const f4v*)p : __builtin_nontemporal_load((const f4v*)p);
+}
+__device__ __forceinline__ void nts4(float2* p, f4v v) { __builtin_nontemporal_store(v, (f4v*)p); }
+__device__ __forceinline__ float2 lo2(f4v v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi2(f4v v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ f4v cat2(float2 a, float2 b) { return f4v{a.x, a.y, b.x, b.y}; }
+// every bit a sign gate fixes is 1 at index idx
+__device__ __forceinline__ bool sign_on(const PgBits& f, int64_t idx) {
+    bool on = true;
+    for (int i = 0; i < f.n; ++i) on = on && ((idx >> f.sh[i]) & 1);
+    return on;
+}
+
+// One item per thread, 16-byte accesses (see PG_VEC_*). Items: diagonal B 2^W / 2,
+// sign and pair updates B 2^(W - fixed) / 2 (PAIRS) or B 2^(W - fixed) (ADJ).
+__global__ __launch_bounds__(256) void k_pg_apply_vec(float2* __restrict__ state, int W, int64_t items,
+                                                      PGate pg, int mode, const float* __restrict__ mats,
+                                                      int n_shared, int n_ps) {
+    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (it >= items) return;
+    if (pg.cls == OP_DIAG) {
+        const int64_t i0 = 2 * it;
+        const int b = (int)(i0 >> W);
+        const M2 M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
+        const f4v a = ntl4(state + i0);
+        float2 u = lo2(a), v = hi2(a);
+        if (pg_ctl_ok(pg, i0)) u = cmul(((i0 >> pg.tsh) & 1) ? M.m11 : M.m00, u);
+        if (pg_ctl_ok(pg, i0 + 1)) v = cmul((((i0 + 1) >> pg.tsh) & 1) ? M.m11 : M.m00, v);
+        nts4(state + i0, cat2(u, v));
+        return;
+    }
+    const PgBits f = pg_bits(pg);
+    if (pg.cls == OP_SIGN) {
+        if (mode == PG_VEC_SWEEP) {
+            const int64_t i0 = 2 * it;
+            const bool n0 = sign_on(f, i0), n1 = sign_on(f, i0 + 1);
+            const f4v a = ntl4(state + i0);
+            nts4(state + i0, f4v{n0 ? -a.x : a.x, n0 ? -a.y : a.y, n1 ? -a.z : a.z, n1 ? -a.w : a.w});
+            return;
+        }
+        const int64_t i0 = pg_index(2 * it, f);  // with its neighbour i0 + 1
+        const f4v a = ntl4(state + i0);
+        nts4(state + i0, f4v{-a.x, -a.y, -a.z, -a.w});
+        return;
+    }
+    M2 M{};
+    if (mode == PG_VEC_ADJ) {
+        const int64_t i0 = pg_index(it, f);
+        if (pg.cls != OP_SWAP) M = load_m2(mat_ptr(mats, pg.mat, (int)(i0 >> W), n_shared, n_ps));
+        const f4v a = ntl4(state + i0);
+        float2 x = lo2(a), y = hi2(a);
+        pair_apply(pg.cls, M, x, y);
+        nts4(state + i0, cat2(x, y));
+        return;
+    }
+    const int64_t i0 = pg_index(2 * it, f), i1 = i0 | (int64_t(1) << pg.tsh);
+    if (pg.cls != OP_SWAP) M = load_m2(mat_ptr(mats, pg.mat, (int)(i0 >> W), n_shared, n_ps));
+    const bool near = pg.tsh <= 3;
+    const f4v a = ld4(state + i0, near), c = ld4(state + i1, near);
+    float2 x0 = lo2(a), x1 = hi2(a), y0 = lo2(c), y1 = hi2(c);
+    pair_apply(pg.cls, M, x0, y0);
+    pair_apply(pg.cls, M, x1, y1);
+    nts4(state + i0, cat2(x0, x1));
+    nts4(state + i1, cat2(y0, y1));
+}
+
 // lambda = D psi_N with D(idx) = sum_i g[b,i] (1 - 2 bit_i(idx)); psi copied to the workspace.
 template <class V>
 __global__ __launch_bounds__(256) void k_adj_init(const V* __restrict__ psiN,
@@ -541,6 +627,108 @@ __global__ __launch_bounds__(256) void k_pg_adj(V* __restrict__ psi, V* __restri
             pair_apply(pg.cls, M, p0, p1);
             pair_apply(pg.cls, M, l0, l1);
             P[i0] = p0; P[i1] = p1; L[i0] = l0; L[i1] = l1;
+        }
+    }
+    if (pg.slot >= 0) {
+        const double r = wave_sum((double)acc);
+        if ((t & 63) == 0) red[t >> 6] = r;
+        __syncthreads();
+        if (t == 0) part[((size_t)pg.slot * B + b) * nch + chunk] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// Plain-method backward step with 16-byte accesses (complex64, PG_VEC_* modes
+// as in k_pg_apply_vec): same arithmetic, partials and grid as k_pg_adj.
+__global__ __launch_bounds__(256) void k_pg_adj_vec(float2* __restrict__ psi, float2* __restrict__ lam, int W,
+                                                    int B, PGate pg, int mode, const float* __restrict__ mats,
+                                                    int n_shared, int n_ps, double* __restrict__ part,
+                                                    int64_t nch) {
+    __shared__ double red[4];
+    constexpr int nt = 256;
+    const int t = threadIdx.x;
+    const int b = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    const size_t off = (size_t)b << W;
+    float2* P = psi + off;
+    float2* L = lam + off;
+    float acc = 0.f;
+    M2 M{};
+    if (pg.cls != OP_SWAP && pg.cls != OP_SIGN) M = load_m2(mat_ptr(mats, pg.mat, b, n_shared, n_ps));
+    auto grad_pair = [&](float2 p0, float2 p1, float2 l0, float2 l1) {
+        if (pg.grad == OP_GX) acc += im_conj_mul(l0, p1) + im_conj_mul(l1, p0);
+        else if (pg.grad == OP_GY) acc += re_conj_mul(l1, p0) - re_conj_mul(l0, p1);
+    };
+    if (pg.cls == OP_DIAG) {
+        const int64_t per = ((int64_t(1) << W) / 2) / nch;  // items of two amplitudes
+        for (int64_t e = t; e < per; e += nt) {
+            const int64_t i0 = 2 * (chunk * per + e);
+            const f4v pa = ntl4(P + i0), la = ntl4(L + i0);
+            float2 p[2] = {lo2(pa), hi2(pa)}, l[2] = {lo2(la), hi2(la)};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int64_t idx = i0 + j;
+                if (!pg_ctl_ok(pg, idx)) continue;
+                const int bit = (idx >> pg.tsh) & 1;
+                if (pg.grad == OP_GZ) acc += bit ? -im_conj_mul(l[j], p[j]) : im_conj_mul(l[j], p[j]);
+                const float2 ph = bit ? M.m11 : M.m00;
+                p[j] = cmul(ph, p[j]);
+                l[j] = cmul(ph, l[j]);
+            }
+            nts4(P + i0, cat2(p[0], p[1]));
+            nts4(L + i0, cat2(l[0], l[1]));
+        }
+    } else if (pg.cls == OP_SIGN && mode == PG_VEC_SWEEP) {
+        const PgBits f = pg_bits(pg);
+        const int64_t per = ((int64_t(1) << W) / 2) / nch;
+        for (int64_t e = t; e < per; e += nt) {
+            const int64_t i0 = 2 * (chunk * per + e);
+            const bool n0 = sign_on(f, i0), n1 = sign_on(f, i0 + 1);
+            const f4v pa = ntl4(P + i0), la = ntl4(L + i0);
+            nts4(P + i0, f4v{n0 ? -pa.x : pa.x, n0 ? -pa.y : pa.y, n1 ? -pa.z : pa.z, n1 ? -pa.w : pa.w});
+            nts4(L + i0, f4v{n0 ? -la.x : la.x, n0 ? -la.y : la.y, n1 ? -la.z : la.z, n1 ? -la.w : la.w});
+        }
+    } else if (pg.cls == OP_SIGN) {
+        const PgBits f = pg_bits(pg);
+        const int64_t per = ((int64_t(1) << (W - f.n)) / 2) / nch;
+        for (int64_t e = t; e < per; e += nt) {
+            const int64_t i0 = pg_index(2 * (chunk * per + e), f);
+            const f4v pa = ntl4(P + i0), la = ntl4(L + i0);
+            nts4(P + i0, f4v{-pa.x, -pa.y, -pa.z, -pa.w});
+            nts4(L + i0, f4v{-la.x, -la.y, -la.z, -la.w});
+        }
+    } else if (mode == PG_VEC_ADJ) {
+        const PgBits f = pg_bits(pg);
+        const int64_t per = (int64_t(1) << (W - f.n)) / nch;
+        for (int64_t e = t; e < per; e += nt) {
+            const int64_t i0 = pg_index(chunk * per + e, f);
+            const f4v pa = ntl4(P + i0), la = ntl4(L + i0);
+            float2 p0 = lo2(pa), p1 = hi2(pa), l0 = lo2(la), l1 = hi2(la);
+            grad_pair(p0, p1, l0, l1);
+            pair_apply(pg.cls, M, p0, p1);
+            pair_apply(pg.cls, M, l0, l1);
+            nts4(P + i0, cat2(p0, p1));
+            nts4(L + i0, cat2(l0, l1));
+        }
+    } else {
+        const PgBits f = pg_bits(pg);
+        const int64_t per = ((int64_t(1) << (W - f.n)) / 2) / nch;
+        const int64_t step = int64_t(1) << pg.tsh;
+        const bool near = pg.tsh <= 3;
+        for (int64_t e = t; e < per; e += nt) {
+            const int64_t i0 = pg_index(2 * (chunk * per + e), f), i1 = i0 | step;
+            const f4v pa = ld4(P + i0, near), pc = ld4(P + i1, near), la = ld4(L + i0, near), lc = ld4(L + i1, near);
+            float2 p00 = lo2(pa), p01 = hi2(pa), p10 = lo2(pc), p11 = hi2(pc);
+            float2 l00 = lo2(la), l01 = hi2(la), l10 = lo2(lc), l11 = hi2(lc);
+            grad_pair(p00, p10, l00, l10);
+            grad_pair(p01, p11, l01, l11);
+            pair_apply(pg.cls, M, p00, p10);
+            pair_apply(pg.cls, M, p01, p11);
+            pair_apply(pg.cls, M, l00, l10);
+            pair_apply(pg.cls, M, l01, l11);
+            nts4(P + i0, cat2(p00, p01));
+            nts4(P + i1, cat2(p10, p11));
+            nts4(L + i0, cat2(l00, l01));
+            nts4(L + i1, cat2(l10, l11));
         }
     }
     if (pg.slot >= 0) {
@@ -1639,6 +1827,21 @@ int pg_prof_class(const PGate& g) {
     return g.cls == OP_DIAG ? 1 : 0;
 }
 constexpr int kPgSub0 = 1000;  // profiler sub-key offset of the per-gate classes
+
+// 16-byte access mode of a per-gate launch on `state` (PG_VEC_*; PG_SCALAR
+// for complex128 states, states not 16-byte aligned, or a fixed bit 0 that is
+// not a pair's target)
+int pg_vec_mode(const qsv_plan_t* p, const PGate& g, const void* state) {
+    if (c128(p) || ((uintptr_t)state & 15)) return PG_SCALAR;
+    if (g.cls == OP_DIAG) return PG_VEC_PAIRS;
+    int lo = 64;
+    for (int sh : {g.tsh, g.cls == OP_SIGN ? g.sh2 : g.csh, g.csh2})
+        if (sh >= 0) lo = std::min(lo, sh);
+    if (g.cls == OP_SIGN && lo <= 2) return PG_VEC_SWEEP;
+    if (lo >= 1) return PG_VEC_PAIRS;
+    if (g.tsh == 0) return PG_VEC_ADJ;
+    return PG_SCALAR;
+}
 const char* const kPgClassNames[4] = {"1q", "diag", "ctl", "sign"};
 
 size_t pass_lds_fwd(const qsv_plan_t* p) {
@@ -1925,12 +2128,20 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
             else items = B << (W - nfix);
             const int64_t blocks = (items + 256 * kPgItems - 1) / (256 * kPgItems);
             hipEvent_t ev = prof_begin(p, s);
-            if (c128(p))
+            const int vmode = pg_vec_mode(p, pg, st);
+            if (vmode != PG_SCALAR) {
+                // one item per thread: two amplitudes (diagonal), two pairs (PAIRS) or one pair (ADJ)
+                const int64_t vitems = (pg.cls == OP_DIAG || vmode == PG_VEC_SWEEP) ? (B << W) / 2
+                                     : vmode == PG_VEC_ADJ ? (B << (W - nfix)) : (B << (W - nfix)) / 2;
+                hipLaunchKernelGGL(k_pg_apply_vec, dim3((unsigned)((vitems + 255) / 256)), dim3(256), 0, s, st, W,
+                                   vitems, pg, vmode, (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+            } else if (c128(p)) {
                 hipLaunchKernelGGL(k_pg_apply<double2>, dim3((unsigned)blocks), dim3(256), 0, s, (double2*)st, W,
                                    B, pg, (const double*)mats, p->n_shared_mats, p->n_ps_mats);
-            else
+            } else {
                 hipLaunchKernelGGL(k_pg_apply<float2>, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
                                    (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+            }
             prof_end(p, s, ev, K_PG_APPLY, 2.0 * (double)amp_size(p) * touched * amps, p->pg_fwd_flops[i] * amps,
                      kPgSub0 + pg_prof_class(pg));
         }
@@ -2120,7 +2331,12 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
             const PGate& pg = p->pg_bwd[i];
             const double touched = pg_touched(pg);
             ev = prof_begin(p, s);
-            if (c128(p))
+            const int vmode = pg_vec_mode(p, pg, psi);
+            if (vmode != PG_SCALAR)
+                hipLaunchKernelGGL(k_pg_adj_vec, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s, psi, lam, W,
+                                   (int)B, pg, vmode, (const float*)mats, p->n_shared_mats, p->n_ps_mats, part,
+                                   nch);
+            else if (c128(p))
                 hipLaunchKernelGGL(k_pg_adj<double2>, dim3((unsigned)nch, (unsigned)B), dim3(256), 0, s,
                                    (double2*)psi, (double2*)lam, W, (int)B, pg, (const double*)mats,
                                    p->n_shared_mats, p->n_ps_mats, part, nch);
