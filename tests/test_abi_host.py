@@ -115,6 +115,11 @@ def test_calls_validate_before_touching_the_device(lib):
     assert L.qsv_forward(h, fake, fake, 2, fake, fake, 8, None) == -1
     assert L.qsv_expval(h, fake, 2, fake, fake, 8, None) == -1
     assert L.qsv_backward(h, fake, fake, 2, fake, fake, fake, 8, fake, fake, None) == -1
+    # forward + readout: workspace too small, null output, null plan
+    assert L.qsv_forward_expval(h, fake, fake, 2, fake, fake, fake, 8, None) == -1
+    assert L.qsv_forward_expval(h, fake, fake, 2, fake, None, fake, big, None) == -1
+    assert L.qsv_forward_expval(None, fake, fake, 2, fake, fake, fake, big, None) == -8
+    assert L.qsv_workspace_size(h, 2, 4) >= L.qsv_workspace_size(h, 2, 0) + L.qsv_workspace_size(h, 2, 1)
     # null pointers
     assert L.qsv_forward(h, None, fake, 2, fake, fake, big, None) == -1
     assert L.qsv_backward(h, fake, fake, 2, None, fake, fake, big, fake, fake, None) == -1
