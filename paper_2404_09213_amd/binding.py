@@ -400,9 +400,13 @@ class Plan:
         return qsv_profile_read(self.handle)
 
     def workspace(self, batch, op, device):
+        """Workspace of kind `op` for the current stream on `device`: calls on
+        different streams get different buffers (the library requires distinct
+        workspaces for calls that may run concurrently); calls on one stream
+        reuse theirs in stream order."""
         import torch
         n = qsv_workspace_size(self.handle, batch, op)
-        key = (op, str(device))
+        key = (op, str(device), torch.cuda.current_stream(device).cuda_stream)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < n:
             ws = torch.empty(max(n, 256), dtype=torch.uint8, device=device)

@@ -140,3 +140,40 @@ def test_graph_rejects_default_stream_and_small_workspace():
     assert rc == -1 and h.value is None
     assert L.qsv_graph_launch(None, None) == -8
     L.qsv_graph_destroy(None)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", ["fused", "per_gate"])
+def test_one_plan_on_two_streams(method):
+    """Two streams share a plan and run forward + readout + backward
+    concurrently on different inputs; each stream gets its own workspace and
+    the results equal the sequential ones bit for bit."""
+    import torch
+    print(f"[graph] two streams {method}", flush=True)
+    dev = torch.device("cuda:0")
+    c = I.rx_ry_rz_cz_ladder(14, 3)
+    plan = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method=method)
+    batch = 6
+    runs = []
+    for seed in (11, 12):
+        w, x = I.draw_angles(c, batch, seed)
+        g = I.draw_grad_out(c, batch, seed)
+        runs.append((torch.from_numpy(w).to(dev), torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)))
+    ref = []
+    for w, x, g in runs:  # sequential, default stream
+        st, E = plan.forward_expval(w, x, batch)
+        gw, gx = plan.backward(w, x, st, g)
+        ref.append((st, E, gw, gx))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    out = [None, None]
+    for r in range(3):  # several rounds, both streams in flight together
+        for i, (w, x, g) in enumerate(runs):
+            with torch.cuda.stream(streams[i]):
+                st, E = plan.forward_expval(w, x, batch)
+                gw, gx = plan.backward(w, x, st, g)
+                out[i] = (st, E, gw, gx)
+        torch.cuda.synchronize()
+        for i in range(2):
+            for got, want in zip(out[i], ref[i]):
+                assert torch.equal(got, want), (r, i)
