@@ -77,7 +77,9 @@ enum {
     QSV_ERR_QUBIT = -2,    /* qubit index out of range, or a gate naming one qubit twice */
     QSV_ERR_GATE = -3,     /* unknown gate kind */
     QSV_ERR_PARAM = -4,    /* angle source / index invalid for the gate */
-    QSV_ERR_TOO_BIG = -5,  /* W > QSV_MAX_QUBITS or the state size overflows */
+    QSV_ERR_TOO_BIG = -5,  /* W > QSV_MAX_QUBITS, the state size overflows, a
+                              launch would exceed HIP's grid limit (see
+                              tile_qubits) or more than 2^24 gradient outputs */
     QSV_ERR_OOM = -6,      /* host or device allocation failed */
     QSV_ERR_HIP = -7,      /* a HIP runtime call failed; see qsv_last_error() */
     QSV_ERR_HANDLE = -8    /* null or destroyed plan */
@@ -113,7 +115,10 @@ typedef struct {
                             packs gate by gate (1-qubit chains, single
                             2-qubit gates), which gives the fewest passes */
     int32_t tile_qubits; /* m: qubits of one tile of amplitudes held by a
-                            workgroup, 4..14 (4..12 when codegen = 0); clamped to W */
+                            workgroup, 4..14 (4..12 when codegen = 0); clamped to W.
+                            A call whose tiles x threads per tile (max(64, 2^(m-4)))
+                            exceed 2^32 returns QSV_ERR_TOO_BIG: below m = 10 that
+                            bounds the batch's amplitudes by 2^(26+m) */
     int32_t low_qubits;  /* c: number of lowest-stride qubits every tile keeps
                             (contiguous runs of 2^c amplitudes); 0..m-1 */
     int32_t max_pass_grads; /* cap on parametric gates per backward pass, 1..256 */

@@ -339,6 +339,16 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
 // ----------------------------------------------------------------------------
 constexpr int kPgItems = 4;
 
+// Launch shape of a one-dimensional grid of n_blocks blocks. HIP bounds the
+// threads of each grid dimension by 2^32, which the whole-batch kernels reach
+// from 2^32 amplitudes (32 GiB of complex64), so blocks beyond 2^16 spill into y.
+// Kernels launched this way read their block number from block_1d().
+static dim3 grid_1d(int64_t n_blocks) {
+    const int64_t gx = std::min<int64_t>(n_blocks, int64_t(1) << 16);
+    return dim3((unsigned)gx, (unsigned)((n_blocks + gx - 1) / gx));
+}
+__device__ __forceinline__ int64_t block_1d() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+
 template <class V>
 __device__ __forceinline__ void pair_apply(int cls, const M2T<V>& M, V& x, V& y) {
     V u, v;
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(256) void k_pg_apply(V* __restrict__ state, int W, 
     // kPgItems items per thread, 256 apart (coalesced). Items touch disjoint
     // amplitudes, so every load of the thread is issued before the first store:
     // several loads in flight per thread instead of one item at a time.
-    const int64_t base = ((int64_t)blockIdx.x * kPgItems) * 256 + threadIdx.x;
+    const int64_t base = (block_1d() * kPgItems) * 256 + threadIdx.x;
     if (pg.cls == OP_DIAG) {
         const int64_t total = B << W;
         V a[kPgItems];
@@ -509,7 +519,7 @@ __device__ __forceinline__ bool sign_on(const PgBits& f, int64_t idx) {
 __global__ __launch_bounds__(256) void k_pg_apply_vec(float2* __restrict__ state, int W, int64_t items,
                                                       PGate pg, int mode, const float* __restrict__ mats,
                                                       int n_shared, int n_ps) {
-    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t it = block_1d() * 256 + threadIdx.x;
     if (it >= items) return;
     if (pg.cls == OP_DIAG) {
         const int64_t i0 = 2 * it;
@@ -562,7 +572,7 @@ template <class V>
 __global__ __launch_bounds__(256) void k_adj_init(const V* __restrict__ psiN,
                                                   V* __restrict__ psi, V* __restrict__ lam,
                                                   int W, int64_t B, const double* __restrict__ g) {
-    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t it = block_1d() * 256 + threadIdx.x;
     if (it >= (B << W)) return;
     const int64_t b = it >> W;
     const int64_t idx = it & ((int64_t(1) << W) - 1);
@@ -1731,9 +1741,27 @@ int check_batch(const qsv_plan_t* p, int64_t B) {
     if (B <= 0) { set_error("batch must be positive"); return QSV_ERR_ARG; }
     if (B > 65535) { set_error("batch above 65535 is not supported"); return QSV_ERR_ARG; }
     if ((uint64_t)B * (uint64_t)row_amps(p) > (uint64_t(1) << 40)) { set_error("state too large"); return QSV_ERR_TOO_BIG; }
+    // a tiled launch has one block per tile; HIP bounds its threads by 2^32
+    const uint64_t kMaxGridThreads = 0xffffffffull;
     if (p->multi) {
-        for (const DCirc& c : p->circ)
+        uint64_t tiles = 0;
+        for (const DCirc& c : p->circ) {
             if ((B << (c.W - c.m)) > (int64_t(1) << 30)) { set_error("too many tiles"); return QSV_ERR_TOO_BIG; }
+            tiles += (uint64_t)B << (c.W - c.m);
+        }
+        if (tiles * 256 > kMaxGridThreads) { set_error("too many tiles in one round"); return QSV_ERR_TOO_BIG; }
+    } else if (p->opts.method != QSV_METHOD_PER_GATE) {
+        const int m = std::min(p->opts.tile_qubits, p->W);
+        const uint64_t threads = (uint64_t)std::max(64, 1 << (m - kRegBits));
+        if (((uint64_t)B << (p->W - m)) * threads > kMaxGridThreads) {
+            set_error("tile_qubits too small for this state size (tiles x threads above 2^32)");
+            return QSV_ERR_TOO_BIG;
+        }
+    }
+    // one gradient-reduction block per weight and per (sample, input)
+    if ((uint64_t)p->n_weights + (uint64_t)B * (uint64_t)std::max(p->n_inputs, 0) > (uint64_t(1) << 24)) {
+        set_error("more than 2^24 gradient outputs");
+        return QSV_ERR_TOO_BIG;
     }
     return QSV_OK;
 }
@@ -2133,13 +2161,13 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
                 // one item per thread: two amplitudes (diagonal), two pairs (PAIRS) or one pair (ADJ)
                 const int64_t vitems = (pg.cls == OP_DIAG || vmode == PG_VEC_SWEEP) ? (B << W) / 2
                                      : vmode == PG_VEC_ADJ ? (B << (W - nfix)) : (B << (W - nfix)) / 2;
-                hipLaunchKernelGGL(k_pg_apply_vec, dim3((unsigned)((vitems + 255) / 256)), dim3(256), 0, s, st, W,
+                hipLaunchKernelGGL(k_pg_apply_vec, grid_1d((vitems + 255) / 256), dim3(256), 0, s, st, W,
                                    vitems, pg, vmode, (const float*)mats, p->n_shared_mats, p->n_ps_mats);
             } else if (c128(p)) {
-                hipLaunchKernelGGL(k_pg_apply<double2>, dim3((unsigned)blocks), dim3(256), 0, s, (double2*)st, W,
+                hipLaunchKernelGGL(k_pg_apply<double2>, grid_1d(blocks), dim3(256), 0, s, (double2*)st, W,
                                    B, pg, (const double*)mats, p->n_shared_mats, p->n_ps_mats);
             } else {
-                hipLaunchKernelGGL(k_pg_apply<float2>, dim3((unsigned)blocks), dim3(256), 0, s, st, W, B, pg,
+                hipLaunchKernelGGL(k_pg_apply<float2>, grid_1d(blocks), dim3(256), 0, s, st, W, B, pg,
                                    (const float*)mats, p->n_shared_mats, p->n_ps_mats);
             }
             prof_end(p, s, ev, K_PG_APPLY, 2.0 * (double)amp_size(p) * touched * amps, p->pg_fwd_flops[i] * amps,
@@ -2321,10 +2349,10 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
         const int64_t n = B << W;
         hipEvent_t ev = prof_begin(p, s);
         if (c128(p))
-            hipLaunchKernelGGL(k_adj_init<double2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_adj_init<double2>, grid_1d((n + 255) / 256), dim3(256), 0, s,
                                (const double2*)d_state, (double2*)psi, (double2*)lam, W, B, gout);
         else
-            hipLaunchKernelGGL(k_adj_init<float2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_adj_init<float2>, grid_1d((n + 255) / 256), dim3(256), 0, s,
                                (const float2*)d_state, psi, lam, W, B, gout);
         prof_end(p, s, ev, K_ADJ_INIT, 3.0 * (double)amp_size(p) * amps, 2.0 * W * amps);
         for (size_t i = 0; i < p->pg_bwd.size(); ++i) {

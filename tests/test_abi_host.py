@@ -131,6 +131,31 @@ def test_calls_validate_before_touching_the_device(lib):
     B.qsv_plan_destroy(h)
 
 
+def test_launch_shapes_beyond_hip_grid_limits_are_rejected(lib):
+    """A tiled pass launches one block per tile; with small tiles on a large
+    state the grid would exceed HIP's 2^32 threads per dimension, which must
+    be reported before anything is launched."""
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    big = 1 << 40
+    c = I.rx_ry_rz_cz_ladder(30, 1)
+    o = B.qsv_default_opts()
+    o.tile_qubits, o.low_qubits = 4, 3  # 64 threads per 16-amplitude tile
+    h = B.qsv_plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, o)
+    assert L.qsv_forward(h, fake, fake, 1, fake, fake, big, None) == -5
+    assert "tile_qubits" in B.qsv_last_error()
+    B.qsv_plan_destroy(h)
+    o.tile_qubits = 10         # 64 threads per 1024 amplitudes: fits
+    h = B.qsv_plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, o)
+    assert L.qsv_forward(h, fake, fake, 1, fake, fake, 8, None) == -1  # only the workspace is short
+    B.qsv_plan_destroy(h)
+    # gradient outputs: one reduction block each
+    c = I.rx_ry_rz_cz_ladder(4, 1)
+    h = B.qsv_plan(c.n_qubits, c.gates, c.n_weights, 1 << 9, None)
+    assert L.qsv_backward(h, fake, fake, 1 << 15, fake, fake, fake, big, fake, fake, None) == -5
+    B.qsv_plan_destroy(h)
+
+
 def test_strerror(lib):
     for code in range(-8, 1):
         assert B.qsv_strerror(code)
