@@ -115,7 +115,7 @@ def counters_traffic(workload, kernel, sha):
         return None, f"counters were taken for {d.get('kernel')}"
     if d.get("codegen_sha1") != sha:
         return None, "kernel source changed since the counters were taken"
-    return d["traffic_bytes"], path
+    return d["traffic_bytes"], os.path.relpath(path, ROOT)
 
 
 def log(args, *a):
