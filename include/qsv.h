@@ -179,7 +179,7 @@ typedef struct {
 
 typedef struct qsv_plan_s qsv_plan_t;
 
-/* Fill *opts with the defaults (fused, k = 1, m = 12, c = 5, 256, codegen 1, chain
+/* Fill *opts with the defaults (fused, k = 1, m = 12, c = 4, 256, codegen 1, chain
  * products in the backward, mfma 1). */
 void qsv_default_opts(qsv_opts* opts);
 

@@ -1915,7 +1915,7 @@ void qsv_default_opts(qsv_opts* o) {
     o->method = QSV_METHOD_FUSED;
     o->fuse_width = 1;
     o->tile_qubits = 12;
-    o->low_qubits = 5;
+    o->low_qubits = 4;
     o->max_pass_grads = 256;
     o->codegen = 1;
     o->mfma = 1;
