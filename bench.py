@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--mfma", type=int, choices=range(8), default=None,
                     help="2x2 products on the matrix cores, bits: 1 forward, 2 backward psi, 4 backward lambda")
     ap.add_argument("--bwd-gate-by-gate", type=int, choices=(0, 1), default=None)
+    ap.add_argument("--pack-beam", type=int, default=None)
     ap.add_argument("--uneven-steps", type=int, default=15,
                     help="timed steps of the 512-circuit uneven set (0 = skip)")
     ap.add_argument("--quiet", action="store_true")
@@ -253,7 +254,8 @@ def main():
     W = circ.n_qubits
     opts = {k: v for k, v in (("fuse_width", args.fuse_width), ("tile_qubits", args.tile_qubits),
                               ("low_qubits", args.low_qubits), ("mfma", args.mfma),
-                              ("bwd_gate_by_gate", args.bwd_gate_by_gate)) if v is not None}
+                              ("bwd_gate_by_gate", args.bwd_gate_by_gate),
+                              ("pack_beam", args.pack_beam)) if v is not None}
     t_plan = time.perf_counter()
     fused = binding.Plan(W, circ.gates, circ.n_weights, circ.n_inputs, method="fused", **opts)
     plan_ms = (time.perf_counter() - t_plan) * 1e3
@@ -372,6 +374,7 @@ def main():
                    "n_gates": len(circ.gates), "n_weights": circ.n_weights,
                    "method": "fused", "fuse_width": info["fuse_width"],
                    "tile_qubits": info["tile_qubits"], "low_qubits": info["low_qubits"],
+                   "pack_beam": opts.get("pack_beam", binding.qsv_default_opts().pack_beam),
                    "fwd_passes": info["n_fwd_passes"], "bwd_passes": info["n_bwd_passes"],
                    "plan_ms": round(plan_ms, 2)},
         "per_gate": pg,

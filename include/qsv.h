@@ -149,7 +149,9 @@ typedef struct {
                             gate matrices, for the plain method only (method =
                             QSV_METHOD_PER_GATE; the same kernels instantiated for
                             double precision). State and workspace sizes double. */
-    int32_t reserved;
+    int32_t pack_beam;   /* fused method: width of the beam search that chooses each
+                            pass's tile qubits (0..256, default 16); 0 packs passes
+                            greedily in program order with no choice of tile */
 } qsv_opts;
 
 /* amplitude types (qsv_opts.amp_dtype) */

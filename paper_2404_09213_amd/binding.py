@@ -48,7 +48,7 @@ class qsv_opts(ctypes.Structure):
                 ("max_pass_grads", ctypes.c_int32), ("codegen", ctypes.c_int32),
                 ("bwd_gate_by_gate", ctypes.c_int32), ("mfma", ctypes.c_int32),
                 ("weight_remap", ctypes.c_int32), ("splitter", ctypes.c_int32),
-                ("amp_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("amp_dtype", ctypes.c_int32), ("pack_beam", ctypes.c_int32)]
 
 
 class qsv_plan_info(ctypes.Structure):
@@ -333,8 +333,10 @@ def qsv_last_error():
 
 def make_opts(method="fused", fuse_width=None, tile_qubits=None, low_qubits=None,
               max_pass_grads=None, codegen=None, bwd_gate_by_gate=None, mfma=None,
-              weight_remap=None, splitter=None, amp_dtype=None):
+              weight_remap=None, splitter=None, amp_dtype=None, pack_beam=None):
     o = qsv_default_opts()
+    if pack_beam is not None:
+        o.pack_beam = int(pack_beam)
     if amp_dtype is not None:
         o.amp_dtype = AMP[amp_dtype] if isinstance(amp_dtype, str) else int(amp_dtype)
     if splitter is not None:

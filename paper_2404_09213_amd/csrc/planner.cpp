@@ -15,7 +15,8 @@
 // 4. Pass builder: blocks are packed into passes; a pass is one read and one
 //    write of the state in tiles of 2^m amplitudes whose qubits cover every
 //    qubit the pass acts on non-diagonally, plus the c lowest-stride qubits.
-//    A block may move ahead of blocks it commutes with.
+//    A block may move ahead of blocks it commutes with. Which qubits each
+//    pass's tile holds is chosen by a small beam search (see pack_passes).
 // 5. Stage builder: inside a pass, each thread keeps 2^4 amplitudes spanning 4
 //    tile qubits in registers; ops are grouped into stages whose non-diagonal
 //    qubits fit those 4 register bits; between stages the tile is re-laid out
@@ -249,48 +250,139 @@ uint32_t low_mask(int W, int c) {
 }
 
 // Pack blocks into passes; returns per pass the gate list in execution order.
+//
+// One pass is one greedy scan of the remaining blocks in order, from a tile
+// seed T0: a block joins when it commutes with every block skipped before it,
+// its dense qubits fit the tile (with T0 and the c low qubits) and the
+// gradient cap allows; the others stay, in order, for later passes. Which
+// qubits a pass's tile holds decides how far later passes get, so the seeds
+// tried are the empty set (the plain program-order greedy), every window of
+// consecutive qubits (in qubit order, wrapping round) and the dense qubits of
+// the first remaining blocks; a beam search over those choices keeps the
+// `beam` sequences that have packed the most gates after each pass (plus the
+// plain greedy sequence) and returns the first that packs everything, i.e.
+// the fewest passes it found, never more than the plain greedy needs.
 std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block> blocks, int m,
                                           int c, int max_grads, std::vector<uint32_t>& pass_dense) {
-    std::vector<std::vector<int>> passes;
     const uint32_t low = low_mask(p->W, c);
-    std::vector<Block> remaining = std::move(blocks);
-    while (!remaining.empty()) {
-        uint32_t T = 0, sD = 0, sC = 0;
+    // a block wider than a tile is packed gate by gate
+    std::vector<Block> bl;
+    for (auto& b : blocks) {
+        if (popc(block_sets(p, b).D | low) <= m) { bl.push_back(b); continue; }
+        for (int g : b.gates) {
+            Block one;
+            one.gates.push_back(g);
+            one.Q = qmask(p->gates[g]);
+            bl.push_back(one);
+        }
+    }
+    const int nb = (int)bl.size();
+    std::vector<BlockSets> bs(nb);
+    for (int i = 0; i < nb; ++i) bs[i] = block_sets(p, bl[i]);
+
+    struct State {
+        std::vector<int> rem;                 // remaining block indices, in order
+        std::vector<std::vector<int>> passes;  // block indices per pass
+        std::vector<uint32_t> dense;
+        int packed = 0;                        // gates packed so far
+        bool greedy = true;                    // every pass so far from the empty seed
+    };
+    // one pass from seed T0 over st.rem: taken blocks, their dense qubits, the rest
+    auto scan = [&](const std::vector<int>& rem, uint32_t T0, std::vector<int>& took, std::vector<int>& left,
+                    uint32_t& T, int& ngate) {
+        uint32_t Tt = T0, sD = 0, sC = 0;
         int ngrad = 0;
-        std::vector<int> gates;
-        std::vector<Block> skipped;
-        bool any = false;
-        for (auto& b : remaining) {
-            BlockSets s = block_sets(p, b);
-            const bool conflict = conflicts(s.D, s.C, sD, sC);
-            if (!conflict && popc(T | s.D | low) <= m && ngrad + s.nparam <= max_grads) {
+        T = 0;
+        ngate = 0;
+        took.clear();
+        left.clear();
+        for (int i : rem) {
+            const BlockSets& s = bs[i];
+            if (!conflicts(s.D, s.C, sD, sC) && popc(Tt | s.D | low) <= m && ngrad + s.nparam <= max_grads) {
+                Tt |= s.D;
                 T |= s.D;
                 ngrad += s.nparam;
-                gates.insert(gates.end(), b.gates.begin(), b.gates.end());
-                any = true;
+                ngate += (int)bl[i].gates.size();
+                took.push_back(i);
             } else {
-                skipped.push_back(b);
+                left.push_back(i);
                 sD |= s.D;
                 sC |= s.C;
             }
         }
-        if (!any) {
-            // The first block alone does not fit a tile: split it into single gates.
-            Block big = remaining.front();
-            std::vector<Block> singles;
-            for (int g : big.gates) {
-                Block one;
-                one.gates.push_back(g);
-                one.Q = qmask(p->gates[g]);
-                singles.push_back(one);
-            }
-            remaining.erase(remaining.begin());
-            remaining.insert(remaining.begin(), singles.begin(), singles.end());
-            continue;
+    };
+    std::vector<int> others;
+    for (int q = 0; q < p->W; ++q)
+        if (!(low >> q & 1)) others.push_back(q);
+    const int free_q = m - popc(low), no = (int)others.size();
+    std::vector<uint32_t> windows;
+    if (free_q > 0 && free_q < no)
+        for (int a = 0; a < no; ++a) {
+            uint32_t w = 0;
+            for (int j = 0; j < free_q; ++j) w |= 1u << others[(a + j) % no];
+            windows.push_back(w);
         }
+    const int beam = p->opts.pack_beam;
+    constexpr int kBlockSeeds = 16;
+
+    State init;
+    for (int i = 0; i < nb; ++i) init.rem.push_back(i);
+    std::vector<State> cur{init};
+    const State* done = nullptr;
+    std::vector<State> next;
+    while (!done) {
+        next.clear();
+        for (const State& st : cur) {
+            std::vector<uint32_t> cand{0};
+            if (beam > 0) {
+                cand.insert(cand.end(), windows.begin(), windows.end());
+                for (int k = 0; k < (int)st.rem.size() && k < kBlockSeeds; ++k) cand.push_back(bs[st.rem[k]].D & ~low);
+            }
+            std::vector<int> took, left;
+            for (uint32_t T0 : cand) {
+                uint32_t T;
+                int n;
+                scan(st.rem, T0, took, left, T, n);
+                if (n == 0) continue;  // cannot happen for seed 0: the first block always fits
+                State ns;
+                ns.rem = left;
+                ns.passes = st.passes;
+                ns.passes.push_back(took);
+                ns.dense = st.dense;
+                ns.dense.push_back(T);
+                ns.packed = st.packed + n;
+                ns.greedy = st.greedy && T0 == 0;
+                next.push_back(std::move(ns));
+            }
+        }
+        // best first (most gates packed; earlier candidate on ties), one state per remaining set
+        std::stable_sort(next.begin(), next.end(), [](const State& a, const State& b) { return a.packed > b.packed; });
+        // The program-order greedy sequence always stays (or a state with the
+        // same remaining blocks), so the result never needs more passes than it.
+        cur.clear();
+        bool have_greedy = false;
+        for (State& ns : next) {
+            const bool full = (int)cur.size() >= std::max(beam, 1);
+            if (full && (have_greedy || !ns.greedy)) continue;
+            bool dup = false;
+            for (const State& k : cur)
+                if (k.rem == ns.rem) { dup = true; break; }
+            if (dup) {
+                have_greedy = have_greedy || ns.greedy;
+                continue;
+            }
+            have_greedy = have_greedy || ns.greedy;
+            cur.push_back(std::move(ns));
+        }
+        for (const State& st : cur)
+            if (st.rem.empty()) { done = &st; break; }
+    }
+    std::vector<std::vector<int>> passes;
+    for (size_t i = 0; i < done->passes.size(); ++i) {
+        std::vector<int> gates;
+        for (int b : done->passes[i]) gates.insert(gates.end(), bl[b].gates.begin(), bl[b].gates.end());
         passes.push_back(gates);
-        pass_dense.push_back(T);
-        remaining = std::move(skipped);
+        pass_dense.push_back(done->dense[i]);
     }
     return passes;
 }

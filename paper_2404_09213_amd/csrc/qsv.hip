@@ -1919,6 +1919,7 @@ void qsv_default_opts(qsv_opts* o) {
     o->max_pass_grads = 256;
     o->codegen = 1;
     o->mfma = 1;
+    o->pack_beam = 16;
 }
 
 int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n_weights,
@@ -1943,6 +1944,7 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.pack_beam < 0 || o.pack_beam > 256) { set_error("pack_beam must be in 0..256"); return QSV_ERR_ARG; }
     if (o.amp_dtype != QSV_AMP_C64 && o.amp_dtype != QSV_AMP_C128) { set_error("amp_dtype must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.amp_dtype == QSV_AMP_C128 && o.method != QSV_METHOD_PER_GATE) {
         set_error("complex128 amplitudes (amp_dtype = 1) need method = per_gate");
@@ -2433,6 +2435,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.mfma < 0 || o.mfma > 7) { set_error("mfma must be in 0..7"); return QSV_ERR_ARG; }
     if (o.weight_remap != 0 && o.weight_remap != 1) { set_error("weight_remap must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
+    if (o.pack_beam < 0 || o.pack_beam > 256) { set_error("pack_beam must be in 0..256"); return QSV_ERR_ARG; }
     if (o.amp_dtype != QSV_AMP_C64) { set_error("multi-circuit plans use complex64 amplitudes (amp_dtype = 0)"); return QSV_ERR_ARG; }
     std::vector<CircuitIn> cs;
     int64_t row = 0;

@@ -74,7 +74,7 @@ def test_plan_rejects(lib, W, gate, code):
 def test_plan_rejects_bad_options(lib):
     for field, val in [("fuse_width", 0), ("fuse_width", 17), ("tile_qubits", 3),
                        ("tile_qubits", 15), ("low_qubits", 12), ("method", 2), ("codegen", 2),
-                       ("max_pass_grads", 0)]:
+                       ("max_pass_grads", 0), ("pack_beam", -1), ("pack_beam", 257)]:
         o = B.qsv_default_opts()
         setattr(o, field, val)
         assert _plan_rc(4, [(0, 0, -1, 0, -1)], opts=o) == -1, field
@@ -253,6 +253,42 @@ def test_schedule_orders_are_valid(orc, lib, method, k, m, cq, splitter):
             if which == 1:
                 order = order[::-1]
             gates = [c.gates[i] for i in order]
+            got = orc.forward(c.n_qubits, gates, w.astype(np.float64), x.astype(np.float64), 2)
+            assert np.max(np.abs(got - ref)) < 1e-12, (c.name, which)
+
+
+def test_pack_beam_never_needs_more_passes(orc, lib):
+    """The beam search over tile seeds against the program-order greedy
+    (pack_beam = 0): never more passes in either direction, fewer on the
+    20-qubit ladder, and the kernels' gate order still gives the circuit's state."""
+    rng = np.random.default_rng(11)
+    cs = [I.rx_ry_rz_cz_ladder(20, 10), I.ry_rz_cnot_ring(16, 8)]
+    cs += [I.random_layers(int(rng.integers(8, 17)), int(rng.integers(2, 9)), rng) for _ in range(6)]
+    cs += [I.random_mixed(int(rng.integers(6, 14)), int(rng.integers(20, 120)), rng) for _ in range(6)]
+    tot = {0: 0, 16: 0}
+    for c in cs:
+        for m, cq in ((12, 4), (8, 2)):
+            n = {}
+            for beam in (0, 16):
+                p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, tile_qubits=m, low_qubits=cq,
+                           pack_beam=beam)
+                i = p.info()
+                n[beam] = (i["n_fwd_passes"], i["n_bwd_passes"])
+                tot[beam] += sum(n[beam])
+            assert n[16][0] <= n[0][0] and n[16][1] <= n[0][1], (c.name, m, cq, n)
+    assert tot[16] < tot[0]
+    c = I.rx_ry_rz_cz_ladder(20, 10)
+    counts = [B.Plan(20, c.gates, c.n_weights, c.n_inputs, pack_beam=b).info() for b in (0, 16)]
+    assert [(i["n_fwd_passes"], i["n_bwd_passes"]) for i in counts] == [(5, 6), (4, 5)]
+    # schedule validity with the greedy packing (the default packing is covered above)
+    for c in cs[2:6]:
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, tile_qubits=8, low_qubits=2, pack_beam=0)
+        w, x = I.draw_angles(c, 2, 3)
+        ref = orc.forward(c.n_qubits, c.gates, w.astype(np.float64), x.astype(np.float64), 2)
+        for which in (0, 1):
+            order = p.gate_order(which)
+            assert sorted(order.tolist()) == list(range(len(c.gates)))
+            gates = [c.gates[i] for i in (order[::-1] if which else order)]
             got = orc.forward(c.n_qubits, gates, w.astype(np.float64), x.astype(np.float64), 2)
             assert np.max(np.abs(got - ref)) < 1e-12, (c.name, which)
 
