@@ -280,12 +280,25 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
     std::vector<BlockSets> bs(nb);
     for (int i = 0; i < nb; ++i) bs[i] = block_sets(p, bl[i]);
 
+    // A search state: the blocks still to pack and the passes so far (a chain
+    // of nodes, so that states share their history).
+    struct Node {
+        int parent;
+        uint32_t T;
+        std::vector<int> took;
+    };
     struct State {
-        std::vector<int> rem;                 // remaining block indices, in order
-        std::vector<std::vector<int>> passes;  // block indices per pass
-        std::vector<uint32_t> dense;
-        int packed = 0;                        // gates packed so far
-        bool greedy = true;                    // every pass so far from the empty seed
+        int node = -1;
+        std::vector<int> rem;  // remaining block indices, in order
+        uint64_t hash = 0;     // of rem
+        int packed = 0;        // gates packed so far
+        bool greedy = true;    // every pass so far from the empty seed
+    };
+    std::vector<Node> nodes;
+    auto hash_of = [](const std::vector<int>& v) {
+        uint64_t h = 1469598103934665603ull;
+        for (int x : v) h = (h ^ (uint64_t)(uint32_t)x) * 1099511628211ull;
+        return h;
     };
     // one pass from seed T0 over st.rem: taken blocks, their dense qubits, the rest
     auto scan = [&](const std::vector<int>& rem, uint32_t T0, std::vector<int>& took, std::vector<int>& left,
@@ -327,38 +340,42 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
 
     State init;
     for (int i = 0; i < nb; ++i) init.rem.push_back(i);
+    init.hash = hash_of(init.rem);
     std::vector<State> cur{init};
-    const State* done = nullptr;
+    int done = -1;
     std::vector<State> next;
-    while (!done) {
+    std::vector<uint32_t> cand;
+    std::vector<int> took, left;
+    while (done < 0) {
         next.clear();
         for (const State& st : cur) {
-            std::vector<uint32_t> cand{0};
+            cand.assign(1, 0u);
             if (beam > 0) {
                 cand.insert(cand.end(), windows.begin(), windows.end());
                 for (int k = 0; k < (int)st.rem.size() && k < kBlockSeeds; ++k) cand.push_back(bs[st.rem[k]].D & ~low);
+                std::sort(cand.begin() + 1, cand.end());
+                cand.erase(std::unique(cand.begin() + 1, cand.end()), cand.end());
             }
-            std::vector<int> took, left;
             for (uint32_t T0 : cand) {
                 uint32_t T;
                 int n;
                 scan(st.rem, T0, took, left, T, n);
                 if (n == 0) continue;  // cannot happen for seed 0: the first block always fits
+                nodes.push_back(Node{st.node, T, took});
                 State ns;
+                ns.node = (int)nodes.size() - 1;
                 ns.rem = left;
-                ns.passes = st.passes;
-                ns.passes.push_back(took);
-                ns.dense = st.dense;
-                ns.dense.push_back(T);
+                ns.hash = hash_of(ns.rem);
                 ns.packed = st.packed + n;
                 ns.greedy = st.greedy && T0 == 0;
                 next.push_back(std::move(ns));
             }
         }
-        // best first (most gates packed; earlier candidate on ties), one state per remaining set
+        // best first (most gates packed; earlier candidate on ties), one state per
+        // remaining set; the program-order greedy sequence always stays (or a
+        // state with the same remaining blocks), so the result never needs more
+        // passes than it
         std::stable_sort(next.begin(), next.end(), [](const State& a, const State& b) { return a.packed > b.packed; });
-        // The program-order greedy sequence always stays (or a state with the
-        // same remaining blocks), so the result never needs more passes than it.
         cur.clear();
         bool have_greedy = false;
         for (State& ns : next) {
@@ -366,23 +383,22 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
             if (full && (have_greedy || !ns.greedy)) continue;
             bool dup = false;
             for (const State& k : cur)
-                if (k.rem == ns.rem) { dup = true; break; }
-            if (dup) {
-                have_greedy = have_greedy || ns.greedy;
-                continue;
-            }
+                if (k.hash == ns.hash && k.rem == ns.rem) { dup = true; break; }
             have_greedy = have_greedy || ns.greedy;
-            cur.push_back(std::move(ns));
+            if (!dup) cur.push_back(std::move(ns));
         }
         for (const State& st : cur)
-            if (st.rem.empty()) { done = &st; break; }
+            if (st.rem.empty()) { done = st.node; break; }
     }
+    std::vector<int> chain;
+    for (int k = done; k >= 0; k = nodes[k].parent) chain.push_back(k);
+    std::reverse(chain.begin(), chain.end());
     std::vector<std::vector<int>> passes;
-    for (size_t i = 0; i < done->passes.size(); ++i) {
+    for (int k : chain) {
         std::vector<int> gates;
-        for (int b : done->passes[i]) gates.insert(gates.end(), bl[b].gates.begin(), bl[b].gates.end());
+        for (int b : nodes[k].took) gates.insert(gates.end(), bl[b].gates.begin(), bl[b].gates.end());
         passes.push_back(gates);
-        pass_dense.push_back(done->dense[i]);
+        pass_dense.push_back(nodes[k].T);
     }
     return passes;
 }
