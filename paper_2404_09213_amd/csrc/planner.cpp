@@ -265,10 +265,14 @@ uint32_t low_mask(int W, int c) {
 std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block> blocks, int m,
                                           int c, int max_grads, std::vector<uint32_t>& pass_dense) {
     const uint32_t low = low_mask(p->W, c);
-    // a block wider than a tile is packed gate by gate
+    // A block wider than a tile, or with more parametric gates than a pass may
+    // hold, is packed gate by gate. A single gate always fits an empty pass (it
+    // acts densely on at most one qubit, c < m, and max_grads >= 1), so every
+    // pass below packs at least the first remaining block.
     std::vector<Block> bl;
     for (auto& b : blocks) {
-        if (popc(block_sets(p, b).D | low) <= m) { bl.push_back(b); continue; }
+        const BlockSets s = block_sets(p, b);
+        if (popc(s.D | low) <= m && s.nparam <= max_grads) { bl.push_back(b); continue; }
         for (int g : b.gates) {
             Block one;
             one.gates.push_back(g);
@@ -277,6 +281,7 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
         }
     }
     const int nb = (int)bl.size();
+    if (nb == 0) return {};
     std::vector<BlockSets> bs(nb);
     for (int i = 0; i < nb; ++i) bs[i] = block_sets(p, bl[i]);
 
@@ -346,7 +351,8 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
     std::vector<State> next;
     std::vector<uint32_t> cand;
     std::vector<int> took, left;
-    while (done < 0) {
+    // each pass packs at least one block, so at most nb passes
+    for (int level = 0; done < 0 && level < nb && !cur.empty(); ++level) {
         next.clear();
         for (const State& st : cur) {
             cand.assign(1, 0u);
@@ -360,7 +366,7 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
                 uint32_t T;
                 int n;
                 scan(st.rem, T0, took, left, T, n);
-                if (n == 0) continue;  // cannot happen for seed 0: the first block always fits
+                if (n == 0) continue;  // never for seed 0: the first block always fits
                 nodes.push_back(Node{st.node, T, took});
                 State ns;
                 ns.node = (int)nodes.size() - 1;
@@ -390,6 +396,7 @@ std::vector<std::vector<int>> pack_passes(const qsv_plan_t* p, std::vector<Block
         for (const State& st : cur)
             if (st.rem.empty()) { done = st.node; break; }
     }
+    if (done < 0) return {};  // unreachable (see above); the caller checks coverage
     std::vector<int> chain;
     for (int k = done; k >= 0; k = nodes[k].parent) chain.push_back(k);
     std::reverse(chain.begin(), chain.end());
@@ -959,9 +966,18 @@ int build_plan(qsv_plan_t* p) {
     const int exch = (1 << m) * 8;
     int max_grads = std::min(o.max_pass_grads, (160 * 1024 - 256 - exch) / (threads / 4 + 8));
     max_grads = std::max(max_grads, 1);
+    // every gate of the packed list must land in exactly one pass
+    auto covers = [](const std::vector<std::vector<int>>& passes, size_t n) {
+        size_t k = 0;
+        for (auto& ps : passes) k += ps.size();
+        if (k == n) return true;
+        set_error("internal error: pass packing did not place every gate");
+        return false;
+    };
     {
         std::vector<uint32_t> dense;
         auto passes = pack_passes(p, split_with(p, body, o.fuse_width), m, c, 1 << 30, dense);
+        if (!covers(passes, body.size())) return QSV_ERR_GATE;
         PassBuilder pb{p, false, {}};
         for (size_t i = 0; i < passes.size(); ++i)
             pb.build(passes[i], dense[i], m, c, i == 0 ? PF_INIT_FWD : 0, p->fwd_pass, p->fwd_order);
@@ -969,6 +985,7 @@ int build_plan(qsv_plan_t* p) {
     {
         std::vector<uint32_t> dense;
         auto passes = pack_passes(p, p->blocks, m, c, max_grads, dense);
+        if (!covers(passes, (size_t)p->n_gates)) return QSV_ERR_GATE;
         PassBuilder pb{p, true, std::vector<int>(W, p->n_gates)};
         for (int g = p->n_gates - 1; g >= 0; --g) {
             const qsv_gate& G = p->gates[g];

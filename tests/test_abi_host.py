@@ -293,6 +293,36 @@ def test_pack_beam_never_needs_more_passes(orc, lib):
             assert np.max(np.abs(got - ref)) < 1e-12, (c.name, which)
 
 
+@pytest.mark.timeout(60)
+def test_packing_terminates_on_degenerate_inputs(orc, lib):
+    """Inputs with nothing to pack or blocks no pass can hold whole: an empty
+    circuit, a circuit that is all product-state prefix (empty forward body),
+    and multi-gate blocks with more parametric gates than max_pass_grads
+    allows (packed gate by gate)."""
+    for W in (5, 13):
+        for beam in (0, 16):
+            p = B.Plan(W, [], 0, 0, pack_beam=beam)
+            i = p.info()
+            assert (i["n_fwd_passes"], i["n_bwd_passes"]) == (0, 0)
+    gates = [("RX", q, -1, "input", q) for q in range(8)] + [("RY", q, -1, "weight", q) for q in range(8)]
+    p = B.Plan(8, gates, 8, 8)
+    i = p.info()
+    assert i["n_prefix_gates"] == 16 and i["n_fwd_passes"] == 0 and i["n_bwd_passes"] >= 1
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        c = I.random_layers(int(rng.integers(6, 11)), 4, rng)
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, fuse_width=4, max_pass_grads=1,
+                   tile_qubits=6, low_qubits=1)
+        w, x = I.draw_angles(c, 2, 3)
+        ref = orc.forward(c.n_qubits, c.gates, w.astype(np.float64), x.astype(np.float64), 2)
+        for which in (0, 1):
+            order = p.gate_order(which)
+            assert sorted(order.tolist()) == list(range(len(c.gates)))
+            gates_o = [c.gates[i] for i in (order[::-1] if which else order)]
+            got = orc.forward(c.n_qubits, gates_o, w.astype(np.float64), x.astype(np.float64), 2)
+            assert np.max(np.abs(got - ref)) < 1e-12
+
+
 def test_prefix_covers_embedding_and_first_layer(lib):
     c = I.rx_ry_rz_cz_ladder(20, 10)
     info = B.Plan(20, c.gates, c.n_weights, c.n_inputs).info()
