@@ -269,6 +269,18 @@ def test_dag_splitter(orc, method, k):
         _check(c, 2, 200 + k, orc, method, fuse_width=k, splitter=1)
 
 
+@pytest.mark.parametrize("method", ["fused", "fused_tables"])
+@pytest.mark.parametrize("beam", [0, 64])
+def test_pass_packing_beams(orc, method, beam):
+    """Pass schedules from the plain program-order greedy (pack_beam = 0) and
+    from a wider search than the default, on a ladder, a ring and a random
+    circuit, at two tile shapes."""
+    rng = np.random.default_rng(300 + beam)
+    for c, m, cq in ((I.rx_ry_rz_cz_ladder(14, 4), 10, 3), (I.ry_rz_cnot_ring(12, 4), 8, 2),
+                     (I.random_mixed(11, 160, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS), 9, 2)):
+        _check(c, 2, 300 + beam, orc, method, pack_beam=beam, tile_qubits=m, low_qubits=cq)
+
+
 C128_TOL = 1e-12   # max-abs on amplitudes and <Z_i> with complex128 amplitudes
 C128_GRAD = 1e-10  # relative on gradients
 
