@@ -344,6 +344,7 @@ constexpr int kPgItems = 4;
 // from 2^32 amplitudes (32 GiB of complex64), so blocks beyond 2^16 spill into y.
 // Kernels launched this way read their block number from block_1d().
 static dim3 grid_1d(int64_t n_blocks) {
+    n_blocks = std::max<int64_t>(n_blocks, 1);  // every kernel launched this way bounds-checks its items
     const int64_t gx = std::min<int64_t>(n_blocks, int64_t(1) << 16);
     return dim3((unsigned)gx, (unsigned)((n_blocks + gx - 1) / gx));
 }
