@@ -23,6 +23,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
@@ -196,6 +197,13 @@ private:
     }
 
     int lq(int j) const { return ps_->lq[j]; }
+
+    // Register bits of the layout a pass loads and stores in: the top three
+    // tile bits, plus tile bit 0 when it is amplitude bit 0 (then a register
+    // pair k, k + 1 holds two adjacent amplitudes), else the fourth-highest.
+    std::array<int, kRegBits> nat_reg() const {
+        return {lq(0) == 0 ? 0 : m_ - 4, m_ - 3, m_ - 2, m_ - 1};
+    }
 
     // global offset of register k (within the sample) in layout L
     int gR(const Layout& L, int k) const {
@@ -535,8 +543,7 @@ private:
         name_ = name;
         const int tb = W_ - m_;
         if (last_fwd_) {
-            const int nat_reg0[kRegBits] = {m_ - 4, m_ - 3, m_ - 2, m_ - 1};
-            o_ << readout_table(make_layout(m_, nat_reg0));
+            o_ << readout_table(make_layout(m_, nat_reg().data()));
         }
         if (bwd_ && ps_->n_gout) {
             // gradient outputs of this pass: ordinal, axis, component slots x/y/z, matrix slot
@@ -575,8 +582,12 @@ private:
         o_ << "  const size_t off = (size_t)b << " << W_ << ";\n"
            << "  const float* mp = mats + ((size_t)n_shared + (size_t)b * n_ps) * 8;\n"
            << "  (void)mp;\n";
-        int nat_reg[kRegBits] = {m_ - 4, m_ - 3, m_ - 2, m_ - 1};
-        Layout nat = make_layout(m_, nat_reg);
+        Layout nat = make_layout(m_, nat_reg().data());
+        // With tile bit 0 = amplitude bit 0 in registers 0 and 1 of each pair,
+        // a thread moves its amplitudes as 16-byte pairs when the array is
+        // 16-byte aligned (a wave-uniform test; 8-byte aligned arrays take
+        // single-amplitude accesses).
+        const bool v16 = lq(0) == 0;
         Layout cur = nat;
         o_ << "  int gT = " << gT_expr(cur) << ";\n";
         for (const std::string& A : arrays_) o_ << "  f2 " << A << "[16];\n";
@@ -584,14 +595,26 @@ private:
             for (const std::string& A : arrays_)
                 o_ << "  for (int k = 0; k < 16; ++k) " << A << "[k] = make_float2(0.f, 0.f);\n";
         auto gload = [&](const std::string& A, const std::string& src) {
-            std::string s;
-            for (int k = 0; k < kRegs; ++k) s += A + "[" + I(k) + "] = " + src + "[gT + " + I(gR(cur, k)) + "]; ";
-            return s;
+            std::string s1;
+            for (int k = 0; k < kRegs; ++k) s1 += A + "[" + I(k) + "] = " + src + "[gT + " + I(gR(cur, k)) + "]; ";
+            if (!v16) return s1;
+            std::string s2;
+            for (int k = 0; k < kRegs; k += 2)
+                s2 += "{ const float4 v_ = *reinterpret_cast<const float4*>(" + src + " + gT + " + I(gR(cur, k)) + "); " +
+                      A + "[" + I(k) + "] = make_float2(v_.x, v_.y); " + A + "[" + I(k + 1) +
+                      "] = make_float2(v_.z, v_.w); } ";
+            return "if (((uintptr_t)(" + src + ") & 15) == 0) { " + s2 + "} else { " + s1 + "}";
         };
         auto gstore = [&](const std::string& A, const std::string& dst) {
-            std::string s;
-            for (int k = 0; k < kRegs; ++k) s += dst + "[gT + " + I(gR(cur, k)) + "] = " + A + "[" + I(k) + "]; ";
-            return s;
+            std::string s1;
+            for (int k = 0; k < kRegs; ++k) s1 += dst + "[gT + " + I(gR(cur, k)) + "] = " + A + "[" + I(k) + "]; ";
+            if (!v16) return s1;
+            std::string s2;
+            for (int k = 0; k < kRegs; k += 2)
+                s2 += "*reinterpret_cast<float4*>(" + dst + " + gT + " + I(gR(cur, k)) + ") = make_float4(" + A + "[" +
+                      I(k) + "].x, " + A + "[" + I(k) + "].y, " + A + "[" + I(k + 1) + "].x, " + A + "[" + I(k + 1) +
+                      "].y); ";
+            return "if (((uintptr_t)(" + dst + ") & 15) == 0) { " + s2 + "} else { " + s1 + "}";
         };
         const int flags = ps_->flags;
         if (!bwd_ && (flags & PF_INIT_FWD)) {

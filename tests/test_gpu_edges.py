@@ -164,3 +164,49 @@ def test_ghz_28(method):
     assert np.abs(got["E"].cpu().numpy()).max() < EXP_TOL
     del got, st
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", list(METHODS))
+def test_state_with_8_byte_alignment(orc, method):
+    """States need only 8-byte alignment: a state that starts 8 bytes into its
+    allocation (so not 16-byte aligned) gives the same results as an aligned
+    one, forward and backward (the kernels' 16-byte accesses are only taken
+    for 16-byte aligned arrays). The fused kernels do the same arithmetic
+    either way (bit-equal results); the plain method switches to its scalar
+    kernels, whose float32 rounding may differ in the last bits, so there
+    both results are held to the oracle instead."""
+    import torch
+    from paper_2404_09213_amd import binding
+    c = I.rx_ry_rz_cz_ladder(12, 3)
+    batch = 3
+    w, x = I.draw_angles(c, batch, 17)
+    g = I.draw_grad_out(c, batch, 17)
+    dev = torch.device("cuda:0")
+    plan = binding.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, **METHODS[method])
+    wt = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    gt = torch.from_numpy(np.ascontiguousarray(g)).to(dev)
+    n = batch << c.n_qubits
+    buf = torch.empty(n + 1, dtype=torch.complex64, device=dev)
+    odd = buf[1:].view(batch, 1 << c.n_qubits)
+    assert odd.data_ptr() % 16 == 8
+    print(f"[align] method={method}", flush=True)
+    plan.forward(wt, xt, batch, odd)
+    st = plan.forward(wt, xt, batch)
+    assert st.data_ptr() % 16 == 0
+    E_odd, E = plan.expval(odd), plan.expval(st)
+    gw_o, gx_o = plan.backward(wt, xt, odd, gt)
+    gw, gx = plan.backward(wt, xt, st, gt)
+    if method != "per_gate":
+        assert torch.equal(odd, st) and torch.equal(E_odd, E)
+        assert torch.equal(gw_o, gw) and torch.equal(gx_o, gx)
+    ref = oracle_run(orc, c, w, x, batch, g)
+    for s_, e_, gw_, gx_ in ((st, E, gw, gx), (odd, E_odd, gw_o, gx_o)):
+        assert np.abs(s_.cpu().numpy() - ref["state"]).max() <= AMP_TOL
+        assert np.abs(e_.cpu().numpy() - ref["E"]).max() <= EXP_TOL
+        ok, rel = grad_close(gw_.cpu().numpy(), ref["gw"])
+        assert ok, ("weights", rel)
+        ok, rel = grad_close(gx_.cpu().numpy(), ref["gx"])
+        assert ok, ("inputs", rel)
+    torch.cuda.synchronize()
