@@ -241,8 +241,9 @@ size_t qsv_workspace_size(const qsv_plan_t* plan, int64_t batch, int32_t op);
  * d_weights: n_weights float32 (may be NULL if n_weights == 0).
  * d_inputs:  batch x n_inputs float32, row-major (may be NULL if n_inputs == 0).
  * d_state:   batch x 2^W complex64 (complex128 with amp_dtype = QSV_AMP_C128),
- *            written; 8-byte alignment suffices, the plain method takes its
- *            16-byte-access kernels when it is 16-byte aligned.
+ *            written; 8-byte alignment suffices. The plain method's kernels
+ *            and the generated fused kernels use 16-byte accesses when it is
+ *            16-byte aligned (any torch allocation is).
  */
 int qsv_forward(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
                 int64_t batch, void* d_state, void* d_ws, size_t ws_bytes, void* stream);
