@@ -154,6 +154,11 @@ def test_launch_shapes_beyond_hip_grid_limits_are_rejected(lib):
     h = B.qsv_plan(c.n_qubits, c.gates, c.n_weights, 1 << 9, None)
     assert L.qsv_backward(h, fake, fake, 1 << 15, fake, fake, fake, big, fake, fake, None) == -5
     B.qsv_plan_destroy(h)
+    # multi-circuit rounds: one 256-thread block per tile of every circuit
+    mp = B.MultiPlan([I.rx_ry_rz_cz_ladder(24, 1), I.rx_ry_rz_cz_ladder(24, 1)])
+    assert L.qsv_forward(mp.handle, fake, fake, 1 << 10, fake, fake, big, None) == -1  # fits; workspace short
+    assert L.qsv_forward(mp.handle, fake, fake, 1 << 11, fake, fake, big, None) == -5  # 2^32 threads
+    assert "round" in B.qsv_last_error()
 
 
 def test_strerror(lib):
