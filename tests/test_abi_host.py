@@ -156,8 +156,8 @@ def test_launch_shapes_beyond_hip_grid_limits_are_rejected(lib):
     B.qsv_plan_destroy(h)
     # multi-circuit rounds: one 256-thread block per tile of every circuit
     mp = B.MultiPlan([I.rx_ry_rz_cz_ladder(24, 1), I.rx_ry_rz_cz_ladder(24, 1)])
-    assert L.qsv_forward(mp.handle, fake, fake, 1 << 10, fake, fake, big, None) == -1  # fits; workspace short
-    assert L.qsv_forward(mp.handle, fake, fake, 1 << 11, fake, fake, big, None) == -5  # 2^32 threads
+    assert L.qsv_forward(mp.handle, fake, fake, 1 << 10, fake, fake, 8, None) == -1  # fits; workspace short
+    assert L.qsv_forward(mp.handle, fake, fake, 1 << 11, fake, fake, 8, None) == -5  # 2^32 threads
     assert "round" in B.qsv_last_error()
 
 
