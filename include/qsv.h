@@ -201,7 +201,10 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
 
 /*
  * Plan for many circuits of different sizes and depths simulated together
- * (the uneven batch). Every circuit is split and scheduled as by qsv_plan
+ * (the uneven batch). Not an operation of the paper: its section "Circuit
+ * Splitting" only motivates it (sub-circuits on disjoint qubit sets can be
+ * executed in parallel); the call is this library's addition for batches of
+ * unrelated circuits. Every circuit is split and scheduled as by qsv_plan
  * (fused method, table-driven kernels, tile_qubits <= 12). qsv_forward and
  * qsv_backward then run pass r of EVERY circuit in one launch ("round r"),
  * one workgroup per (circuit, tile); a circuit's next pass is in the next
@@ -237,13 +240,23 @@ void qsv_plan_destroy(qsv_plan_t* plan);
 size_t qsv_workspace_size(const qsv_plan_t* plan, int64_t batch, int32_t op);
 
 /*
- * Forward: d_state[b] = U_N ... U_1 |0...0> for b < batch.
+ * Forward: d_state[b] = U_N ... U_1 |0...0> for b < batch (section "State
+ * Vector Simulation": the gates applied in order to the state vector, each as
+ * the 2x2 / 4x4 update of section "Concept of Shapes", with the gate matrices
+ * of section "Gate Matrix Caching" and the blocks of section "Circuit
+ * Splitting").
  * d_weights: n_weights float32 (may be NULL if n_weights == 0).
  * d_inputs:  batch x n_inputs float32, row-major (may be NULL if n_inputs == 0).
  * d_state:   batch x 2^W complex64 (complex128 with amp_dtype = QSV_AMP_C128),
  *            written; 8-byte alignment suffices. The plain method's kernels
  *            and the generated fused kernels use 16-byte accesses when it is
  *            16-byte aligned (any torch allocation is).
+ * d_ws:      at least qsv_workspace_size(plan, batch, QSV_OP_FORWARD) bytes of
+ *            device memory, 256-byte aligned, owned by the caller. It receives
+ *            the gate matrices evaluated for this call (per sample for gates
+ *            driven by inputs). The paper's signature has no workspace; it is
+ *            taken here so that concurrent calls on one plan share no mutable
+ *            device memory and no call allocates.
  */
 int qsv_forward(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
                 int64_t batch, void* d_state, void* d_ws, size_t ws_bytes, void* stream);
@@ -273,13 +286,20 @@ int qsv_forward_expval(const qsv_plan_t* plan, const float* d_weights, const flo
 
 /*
  * Adjoint backward of L = sum_{b,i} g[b,i] E[b,i], g = d_grad_out (batch x W
- * float64). d_state holds psi_N from qsv_forward with the same weights and
+ * float64). Not the paper's method: it trains through PyTorch's automatic
+ * differentiation (section "Hybrid Machine Learning"), which stores every
+ * intermediate state; this call is the adjoint method added by this library,
+ * which needs two state-sized buffers whatever the depth, and it gives the
+ * same gradients up to rounding. d_state holds psi_N from qsv_forward with the same weights and
  * inputs; it is read, not modified. Going back over the gates, the angle
  * derivative of gate k is Im <lambda_k| P_k |psi_k> with lambda = (sum_i g_i
  * Z_i) psi_N and P_k the gate's generator; psi and lambda are then multiplied
  * by U_k^dagger (uncomputed) instead of being stored per gate.
  * d_grad_weights: n_weights float64, overwritten (summed over the batch).
  * d_grad_inputs:  batch x n_inputs float64, overwritten; may be NULL.
+ * d_ws: at least qsv_workspace_size(plan, batch, QSV_OP_BACKWARD) bytes,
+ *       256-byte aligned: gate matrices, the psi and lambda copies (one state
+ *       each) and float64 gradient partials.
  */
 int qsv_backward(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
                  int64_t batch, const void* d_state, const double* d_grad_out,
