@@ -2013,16 +2013,22 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
 void qsv_plan_destroy(qsv_plan_t* p) {
     if (!p || p->magic != kPlanMagic) return;
     p->magic = 0;
-    int cur = 0;
-    const bool have = hipGetDevice(&cur) == hipSuccess;
-    for (auto& kv : p->dev) {
-        if (hipSetDevice(kv.first) == hipSuccess) {
-            for (void* m : kv.second.modules) (void)hipModuleUnload((hipModule_t)m);
-            for (auto& q : kv.second.queues) (void)hipFree(q.mem);
-            (void)hipFree(kv.second.base);
+    // no HIP call at all for a plan that never ran on a device: a host-only
+    // user of the library must not initialise the HIP runtime (in a process
+    // where another HIP runtime, such as the one bundled with PyTorch, has not
+    // opened the GPU yet, that can leave the GPU unusable for the other one)
+    if (!p->dev.empty()) {
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        for (auto& kv : p->dev) {
+            if (hipSetDevice(kv.first) == hipSuccess) {
+                for (void* m : kv.second.modules) (void)hipModuleUnload((hipModule_t)m);
+                for (auto& q : kv.second.queues) (void)hipFree(q.mem);
+                (void)hipFree(kv.second.base);
+            }
         }
+        if (have) (void)hipSetDevice(cur);
     }
-    if (have && !p->dev.empty()) (void)hipSetDevice(cur);
     if (Profiler* pr = prof_of(p)) {
         for (auto& r : pr->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pr->pool) (void)hipEventDestroy(e);
