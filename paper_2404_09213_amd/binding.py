@@ -87,6 +87,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise OSError(f"libqsv.so not found at {LIB_PATH}; run __graft_entry__.build()")
+        # PyTorch bundles its own HIP runtime under the same library name as
+        # the system one that libqsv.so was linked against. Loading torch first
+        # makes libqsv.so bind to that runtime, so the process has one HIP
+        # runtime; two separate runtimes in one process would each try to own
+        # the GPU, and the one initialised second finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.qsv_default_opts.argtypes = [ctypes.POINTER(qsv_opts)]
