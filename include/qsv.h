@@ -285,6 +285,32 @@ int qsv_forward_expval(const qsv_plan_t* plan, const float* d_weights, const flo
                        void* stream);
 
 /*
+ * qsv_forward_expval without a workspace argument, for callers that cannot
+ * allocate device memory where they call it (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). Same kernels and
+ * results as qsv_forward_expval. Its workspace is a file-scope device array of
+ * QSV_NOALLOC_SCRATCH_BYTES bytes inside the library: one per GPU the library
+ * runs on, held by that GPU until the process ends; the call looks up its
+ * address once per device (on its first call there) and never calls hipMalloc,
+ * hipFree or anything else that allocates; profiling records nothing.
+ *  - The plan's tables must already exist on the current device: an earlier
+ *    qsv_forward, qsv_forward_expval, qsv_expval, qsv_backward or
+ *    qsv_graph_create call on this device creates them (for a multi-circuit
+ *    plan, at this batch size). Otherwise QSV_ERR_ARG, nothing enqueued.
+ *  - A plan and batch whose workspace, qsv_workspace_size(plan, batch,
+ *    QSV_OP_FORWARD_EXPVAL), exceeds QSV_NOALLOC_SCRATCH_BYTES return
+ *    QSV_ERR_TOO_BIG before anything is enqueued.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents (each call writes everything it reads, so nothing needs
+ *    clearing). Calls that may overlap on one GPU (other streams, threads or
+ *    plans) race: the caller must order them.
+ * Other arguments and errors as for qsv_forward_expval.
+ */
+#define QSV_NOALLOC_SCRATCH_BYTES (16 * 1024 * 1024)
+int qsv_forward_expval_noalloc(const qsv_plan_t* plan, const float* d_weights, const float* d_inputs,
+                               int64_t batch, void* d_state, double* d_out, void* stream);
+
+/*
  * Adjoint backward of L = sum_{b,i} g[b,i] E[b,i], g = d_grad_out (batch x W
  * float64). Not the paper's method: it trains through PyTorch's automatic
  * differentiation (section "Hybrid Machine Learning"), which stores every

@@ -72,7 +72,8 @@ class qsv_kernel_stat(ctypes.Structure):
 
 EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets", "qsv_state_offset",
            "qsv_plan_destroy", "qsv_workspace_size",
-           "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_backward", "qsv_plan_get_info",
+           "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_forward_expval_noalloc",
+           "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
            "qsv_plan_codegen_check", "qsv_plan_estimate", "qsv_graph_create", "qsv_graph_launch",
            "qsv_graph_destroy", "qsv_profile_enable",
@@ -121,6 +122,8 @@ def lib():
         L.qsv_expval.restype = ctypes.c_int
         L.qsv_forward_expval.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
         L.qsv_forward_expval.restype = ctypes.c_int
+        L.qsv_forward_expval_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.qsv_forward_expval_noalloc.restype = ctypes.c_int
         L.qsv_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp, vp, vp]
         L.qsv_backward.restype = ctypes.c_int
         L.qsv_plan_get_info.argtypes = [vp, ctypes.POINTER(qsv_plan_info)]
@@ -239,6 +242,11 @@ def qsv_expval(h, d_state, batch, d_out, d_ws, ws_bytes, stream):
 def qsv_forward_expval(h, d_weights, d_inputs, batch, d_state, d_out, d_ws, ws_bytes, stream):
     return _check(lib().qsv_forward_expval(h, d_weights, d_inputs, int(batch), d_state, d_out, d_ws,
                                            int(ws_bytes), stream))
+
+
+def qsv_forward_expval_noalloc(h, d_weights, d_inputs, batch, d_state, d_out, stream):
+    return _check(lib().qsv_forward_expval_noalloc(h, d_weights, d_inputs, int(batch), d_state, d_out,
+                                                   stream))
 
 
 def qsv_backward(h, d_weights, d_inputs, batch, d_state, d_grad_out, d_ws, ws_bytes,
@@ -465,6 +473,15 @@ class Plan:
         ws = self.workspace(batch, OP_FORWARD_EXPVAL, dev)
         qsv_forward_expval(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
                            self._ptr(state), self._ptr(out), self._ptr(ws), ws.numel(), self._stream(dev))
+        return state, out
+
+    def forward_expval_noalloc(self, weights, inputs, batch, state, out):
+        """forward_expval() on the library's own scratch array: no workspace is
+        allocated, so state and out must be given (and the plan must have run
+        once on this device, which creates its tables)."""
+        dev = state.device
+        qsv_forward_expval_noalloc(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
+                                   self._ptr(state), self._ptr(out), self._stream(dev))
         return state, out
 
     def backward(self, weights, inputs, state, grad_out, want_inputs=True, gw=None, gx=None):

@@ -30,6 +30,7 @@ using namespace qsv;
 // ----------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 static thread_local bool g_capturing = false;  // inside qsv_graph_create: no profiling events
+static thread_local bool g_noalloc = false;    // inside qsv_forward_expval_noalloc: nothing may be created
 
 namespace qsv {
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -1545,7 +1546,7 @@ Profiler* prof_of(const qsv_plan_t* p) { return static_cast<Profiler*>(p->prof);
 // Returns the start event (or nullptr when profiling is off).
 hipEvent_t prof_begin(const qsv_plan_t* p, hipStream_t s) {
     Profiler* pr = prof_of(p);
-    if (!pr || !pr->on || g_capturing) return nullptr;
+    if (!pr || !pr->on || g_capturing || g_noalloc) return nullptr;
     std::lock_guard<std::mutex> lk(pr->mu);
     hipEvent_t e = nullptr;
     if (!pr->pool.empty()) { e = pr->pool.back(); pr->pool.pop_back(); }
@@ -1579,6 +1580,11 @@ int get_tables(const qsv_plan_t* p, DeviceTables** out) {
     if (it != p->dev.end()) {
         *out = &it->second;
         return QSV_OK;
+    }
+    if (g_noalloc) {
+        set_error("the plan has no tables on this device yet: an allocation-free call needs an earlier "
+                  "call that creates them (any forward, readout or backward call on this device)");
+        return QSV_ERR_ARG;
     }
     DeviceTables t;
     const size_t sizes[] = {bytes_of(p->dgates), bytes_of(p->recipes), bytes_of(p->recipe_gates),
@@ -1774,6 +1780,11 @@ int get_queue(const qsv_plan_t* p, DeviceTables* T, int64_t B, DeviceTables::Que
     std::lock_guard<std::mutex> lk(p->dev_mu);
     for (auto& q : T->queues)
         if (q.B == B) { *out = &q; return QSV_OK; }
+    if (g_noalloc) {
+        set_error("the multi-circuit plan has no work lists for this batch size on this device yet: an "
+                  "allocation-free call needs an earlier call at this batch size");
+        return QSV_ERR_ARG;
+    }
     std::vector<int> order(p->circ.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->circ[a].W > p->circ[b].W; });
@@ -2256,6 +2267,60 @@ int qsv_forward_expval(const qsv_plan_t* p, const float* w, const float* x, int6
     prof_end(p, s, ev, K_EXPVAL_FINAL, 8.0 * (double)B * ntiles * p->W, 0.0);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
+}
+
+// The workspace of qsv_forward_expval_noalloc: a file-scope device array,
+// one copy per GPU, created with the library's code object on that GPU and
+// held until the process ends. In host code `scratch` names a host-side
+// stand-in, so its device address is looked up once per device (with that
+// device current) and only that address is ever passed on.
+static __device__ __align__(256) unsigned char scratch[QSV_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;
+
+static int scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return QSV_ERR_HIP;
+        }
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return QSV_OK;
+}
+
+int qsv_forward_expval_noalloc(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
+                               double* out, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if ((rc = check_batch(p, B))) return rc;
+    if (!d_state || !out || (p->n_weights && !w) || (p->n_inputs && !x)) {
+        set_error("null pointer");
+        return QSV_ERR_ARG;
+    }
+    const size_t need = qsv_workspace_size(p, B, QSV_OP_FORWARD_EXPVAL);
+    if (need > (size_t)QSV_NOALLOC_SCRATCH_BYTES) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "this plan and batch need %zu bytes of scratch, above the %zu-byte "
+                      "limit of the allocation-free call", need, (size_t)QSV_NOALLOC_SCRATCH_BYTES);
+        set_error(buf);
+        return QSV_ERR_TOO_BIG;
+    }
+    void* ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    // the same launches as qsv_forward_expval on the scratch array; g_noalloc
+    // turns every lazy creation (tables, kernels, work lists, events) into an error
+    g_noalloc = true;
+    rc = qsv_forward_expval(p, w, x, B, d_state, out, ws, (size_t)QSV_NOALLOC_SCRATCH_BYTES, stream);
+    g_noalloc = false;
+    return rc;
 }
 
 int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out, void* ws,
