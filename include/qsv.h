@@ -233,7 +233,10 @@ int qsv_plan_circuit_offsets(const qsv_plan_t* plan, int32_t circuit, int64_t* a
  * range). */
 int64_t qsv_state_offset(const qsv_plan_t* plan, int32_t circuit);
 
-/* Release a plan and its device tables. NULL is ignored. */
+/* Release a plan and its device tables. NULL, an already destroyed plan and
+ * any pointer that is not a live plan are ignored: handles are checked
+ * against the library's registry of live plans (and graphs), never read
+ * through, so every call with a destroyed handle returns QSV_ERR_HANDLE. */
 void qsv_plan_destroy(qsv_plan_t* plan);
 
 /* Bytes of workspace one call of kind `op` (QSV_OP_*) needs at this batch size. */

@@ -32,6 +32,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qsv_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+_CLANG = "/opt/rocm/llvm/bin/clang"
 
 # oracle-private gate numbering (must match the enum in qsv_oracle.c)
 KIND_CODE = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6,
@@ -45,8 +47,22 @@ SRC_CODE = {"none": 0, "weight": 1, "input": 2}
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile qsv_oracle.c with gcc into liboracle.so next to it."""
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile qsv_oracle.c with gcc into liboracle.so next to it.
+
+    sanitize: build liboracle_san.so instead, with clang's AddressSanitizer and
+    UndefinedBehaviorSanitizer (the runtime of the sanitized libqsv build, so
+    both can be loaded into one CPU test process; select it with
+    QSV_ORACLE_LIB=<path>)."""
+    if sanitize:
+        tmp = _LIB_SAN + ".tmp"
+        llvm_lib = os.path.join(os.path.dirname(os.path.dirname(_CLANG)), "lib")
+        subprocess.check_call([_CLANG, "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                               "-fno-omit-frame-pointer", "-Wl,-rpath," + llvm_lib,
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_SAN)
+        return _LIB_SAN
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
@@ -58,9 +74,10 @@ def build(force: bool = False) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("QSV_ORACLE_LIB") or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         ip = ctypes.POINTER(ctypes.c_int)
         dp = ctypes.POINTER(ctypes.c_double)
         vp = ctypes.c_void_p

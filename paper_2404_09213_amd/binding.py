@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqsv.so")
+# QSV_LIB selects another build of the same library (the sanitizer build of
+# build_lib --sanitize, for CPU test runs)
+LIB_PATH = os.environ.get("QSV_LIB") or os.path.join(_HERE, "libqsv.so")
 
 KIND = {"H": 0, "X": 1, "Y": 2, "Z": 3, "RX": 4, "RY": 5, "RZ": 6, "CNOT": 7, "CZ": 8, "CRX": 9,
         "CRY": 10, "CRZ": 11, "CCX": 12, "CCZ": 13, "CCRX": 14}

@@ -93,6 +93,7 @@ public:
         return R"(
 typedef float2 f2;
 typedef float qsv_v4f __attribute__((ext_vector_type(4)));
+typedef __UINTPTR_TYPE__ qsv_uptr;  // pointer-sized integer without any header
 // float64 wavefront sum by DPP lane moves: pairs, quads, half rows, rows, then
 // row 0 -> 1, 2 -> 3 and rows 0-1 -> 2-3 broadcasts; lane 63 holds the total.
 template <int CTRL, int ROWMASK>
@@ -603,7 +604,7 @@ private:
                 s2 += "{ const float4 v_ = *reinterpret_cast<const float4*>(" + src + " + gT + " + I(gR(cur, k)) + "); " +
                       A + "[" + I(k) + "] = make_float2(v_.x, v_.y); " + A + "[" + I(k + 1) +
                       "] = make_float2(v_.z, v_.w); } ";
-            return "if (((uintptr_t)(" + src + ") & 15) == 0) { " + s2 + "} else { " + s1 + "}";
+            return "if (((qsv_uptr)(" + src + ") & 15) == 0) { " + s2 + "} else { " + s1 + "}";
         };
         auto gstore = [&](const std::string& A, const std::string& dst) {
             std::string s1;
@@ -614,7 +615,7 @@ private:
                 s2 += "*reinterpret_cast<float4*>(" + dst + " + gT + " + I(gR(cur, k)) + ") = make_float4(" + A + "[" +
                       I(k) + "].x, " + A + "[" + I(k) + "].y, " + A + "[" + I(k + 1) + "].x, " + A + "[" + I(k + 1) +
                       "].y); ";
-            return "if (((uintptr_t)(" + dst + ") & 15) == 0) { " + s2 + "} else { " + s1 + "}";
+            return "if (((qsv_uptr)(" + dst + ") & 15) == 0) { " + s2 + "} else { " + s1 + "}";
         };
         const int flags = ps_->flags;
         if (!bwd_ && (flags & PF_INIT_FWD)) {

@@ -184,7 +184,6 @@ struct DeviceTables {
 }  // namespace qsv
 
 struct qsv_plan_s {
-    uint32_t magic;
     int W, n_gates, n_weights, n_inputs;
     qsv_opts opts;
     std::vector<qsv_gate> gates;
@@ -255,7 +254,6 @@ inline int64_t pg_chunks(int W) {
     const int64_t q = int64_t(1) << (W - 2 > 0 ? W - 2 : 0);
     return q / 1024 > 1 ? q / 1024 : 1;
 }
-constexpr uint32_t kPlanMagic = 0x51535650u;  // "QSVP"
 int build_plan(qsv_plan_t* p);  // planner.cpp
 struct CircuitIn { int W; const qsv_gate* gates; int n_gates, n_weights, n_inputs; };
 int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs);  // planner.cpp

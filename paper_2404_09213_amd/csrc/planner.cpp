@@ -1027,7 +1027,6 @@ int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs) {
     for (size_t c = 0; c < cs.size(); ++c) {
         const CircuitIn& ci = cs[c];
         qsv_plan_t sub;
-        sub.magic = kPlanMagic;
         sub.W = ci.W;
         sub.n_gates = ci.n_gates;
         sub.n_weights = ci.n_weights;

@@ -12,6 +12,7 @@
 //   k_expval_part / k_expval_final   <Z_i> readout, two deterministic stages
 //   k_grad_reduce   gradient partials -> weight (batch-summed) and input gradients
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cstdio>
@@ -19,6 +20,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <unordered_set>
 
 #include "jit.hpp"
 #include "plan.hpp"
@@ -35,6 +37,15 @@ static thread_local bool g_noalloc = false;    // inside qsv_forward_expval_noal
 namespace qsv {
 void set_error(const std::string& msg) { g_last_error = msg; }
 }
+
+// A roctx range around one library call (planning, forward, readout,
+// backward, graph capture and replay), shown by rocprofv3 --marker-trace.
+// None inside the allocation-free call, which must not call into a tool.
+struct TraceRange {
+    bool on;
+    explicit TraceRange(const char* name) : on(!g_noalloc) { if (on) roctxRangePushA(name); }
+    ~TraceRange() { if (on) roctxRangePop(); }
+};
 
 #define HIP_TRY(expr)                                                            \
     do {                                                                         \
@@ -1700,8 +1711,29 @@ size_t partial_bytes(const qsv_plan_t* p, int64_t B) {
 
 
 
+// Live handles: every plan and graph returned to a caller and not yet
+// destroyed. A handle is checked by looking it up here, never by reading
+// through it, so a destroyed (freed) handle is rejected without touching
+// its memory. A new object that happens to reuse a destroyed one's address
+// is live again: the registry cannot tell the two apart.
+std::mutex g_handles_mu;
+std::unordered_set<const void*> g_live_plans, g_live_graphs;
+
+void handle_add(std::unordered_set<const void*>& set, const void* h) {
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    set.insert(h);
+}
+bool handle_live(const std::unordered_set<const void*>& set, const void* h) {
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    return h && set.count(h) != 0;
+}
+bool handle_remove(std::unordered_set<const void*>& set, const void* h) {
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    return h && set.erase(h) != 0;
+}
+
 int check_plan(const qsv_plan_t* p) {
-    if (!p || p->magic != kPlanMagic) {
+    if (!handle_live(g_live_plans, p)) {
         set_error("null or destroyed plan");
         return QSV_ERR_HANDLE;
     }
@@ -1936,6 +1968,7 @@ void qsv_default_opts(qsv_opts* o) {
 
 int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n_weights,
              int32_t n_inputs, const qsv_opts* opts, qsv_plan_t** out) {
+    TraceRange trace_("qsv_plan");
     if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
     *out = nullptr;
     if (n_qubits < 1) { set_error("n_qubits must be >= 1"); return QSV_ERR_ARG; }
@@ -1998,7 +2031,6 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
     }
     qsv_plan_t* p = new (std::nothrow) qsv_plan_t();
     if (!p) { set_error("plan allocation failed"); return QSV_ERR_OOM; }
-    p->magic = kPlanMagic;
     p->W = n_qubits;
     p->n_gates = n_gates;
     p->n_weights = n_weights;
@@ -2017,13 +2049,13 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
         delete p;
         return rc;
     }
+    handle_add(g_live_plans, p);
     *out = p;
     return QSV_OK;
 }
 
 void qsv_plan_destroy(qsv_plan_t* p) {
-    if (!p || p->magic != kPlanMagic) return;
-    p->magic = 0;
+    if (!handle_remove(g_live_plans, p)) return;  // NULL, destroyed or never a plan
     // no HIP call at all for a plan that never ran on a device: a host-only
     // user of the library must not initialise the HIP runtime (in a process
     // where another HIP runtime, such as the one bundled with PyTorch, has not
@@ -2226,6 +2258,7 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
 
 int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
                 void* ws, size_t ws_bytes, void* stream) {
+    TraceRange trace_("qsv_forward");
     int rc = check_plan(p);
     if (rc) return rc;
     if ((rc = check_batch(p, B))) return rc;
@@ -2239,6 +2272,7 @@ int qsv_forward(const qsv_plan_t* p, const float* w, const float* x, int64_t B, 
 
 int qsv_forward_expval(const qsv_plan_t* p, const float* w, const float* x, int64_t B, void* d_state,
                        double* out, void* ws, size_t ws_bytes, void* stream) {
+    TraceRange trace_("qsv_forward_expval");
     int rc = check_plan(p);
     if (rc) return rc;
     if ((rc = check_batch(p, B))) return rc;
@@ -2325,6 +2359,7 @@ int qsv_forward_expval_noalloc(const qsv_plan_t* p, const float* w, const float*
 
 int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out, void* ws,
                size_t ws_bytes, void* stream) {
+    TraceRange trace_("qsv_expval");
     int rc = check_plan(p);
     if (rc) return rc;
     if ((rc = check_batch(p, B))) return rc;
@@ -2372,6 +2407,7 @@ int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out,
 int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
                  const void* d_state, const double* gout, void* ws, size_t ws_bytes, double* gw,
                  double* gx, void* stream) {
+    TraceRange trace_("qsv_backward");
     int rc = check_plan(p);
     if (rc) return rc;
     if ((rc = check_batch(p, B))) return rc;
@@ -2491,6 +2527,7 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
 
 int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* opts,
                    qsv_plan_t** out) {
+    TraceRange trace_("qsv_plan_multi");
     if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
     *out = nullptr;
     if (!circuits || n_circuits < 1) { set_error("need at least one circuit"); return QSV_ERR_ARG; }
@@ -2526,7 +2563,6 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (row > (int64_t(1) << 34)) { set_error("circuits too large together"); return QSV_ERR_TOO_BIG; }
     qsv_plan_t* p = new (std::nothrow) qsv_plan_t();
     if (!p) { set_error("plan allocation failed"); return QSV_ERR_OOM; }
-    p->magic = kPlanMagic;
     p->opts = o;
     int W = 0;
     for (auto& c : cs) W = std::max(W, c.W);
@@ -2542,6 +2578,7 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
         delete p;
         return rc;
     }
+    handle_add(g_live_plans, p);
     *out = p;
     return QSV_OK;
 }
@@ -2574,16 +2611,15 @@ int64_t qsv_state_offset(const qsv_plan_t* p, int32_t circuit) {
 }
 
 struct qsv_graph_s {
-    uint32_t magic;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
 
-constexpr uint32_t kGraphMagic = 0x51535647u;  // "QSVG"
 
 int qsv_graph_create(const qsv_plan_t* p, int64_t B, const float* w, const float* x, void* d_state,
                      double* d_expval, const double* gout, double* gw, double* gx, void* ws,
                      size_t ws_bytes, void* stream, qsv_graph_t** out) {
+    TraceRange trace_("qsv_graph_create");
     int rc = check_plan(p);
     if (rc) return rc;
     if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
@@ -2625,26 +2661,27 @@ int qsv_graph_create(const qsv_plan_t* p, int64_t B, const float* w, const float
         set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
         return QSV_ERR_HIP;
     }
-    qsv_graph_t* g = new (std::nothrow) qsv_graph_t{kGraphMagic, graph, exec};
+    qsv_graph_t* g = new (std::nothrow) qsv_graph_t{graph, exec};
     if (!g) {
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
         set_error("graph allocation failed");
         return QSV_ERR_OOM;
     }
+    handle_add(g_live_graphs, g);
     *out = g;
     return QSV_OK;
 }
 
 int qsv_graph_launch(qsv_graph_t* g, void* stream) {
-    if (!g || g->magic != kGraphMagic) { set_error("null or destroyed graph"); return QSV_ERR_HANDLE; }
+    TraceRange trace_("qsv_graph_launch");
+    if (!handle_live(g_live_graphs, g)) { set_error("null or destroyed graph"); return QSV_ERR_HANDLE; }
     HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
     return QSV_OK;
 }
 
 void qsv_graph_destroy(qsv_graph_t* g) {
-    if (!g || g->magic != kGraphMagic) return;
-    g->magic = 0;
+    if (!handle_remove(g_live_graphs, g)) return;
     (void)hipGraphExecDestroy(g->exec);
     (void)hipGraphDestroy(g->graph);
     delete g;

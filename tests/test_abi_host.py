@@ -131,6 +131,41 @@ def test_calls_validate_before_touching_the_device(lib):
     B.qsv_plan_destroy(h)
 
 
+def test_use_after_destroy_is_rejected_without_touching_the_plan(lib):
+    """A destroyed handle (and any pointer that was never a handle) is looked
+    up in the library's registry of live handles, not read through, so every
+    call returns QSV_ERR_HANDLE and a second destroy is ignored (under
+    AddressSanitizer this also shows that no freed memory is read)."""
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    big = 1 << 30
+    info = B.qsv_plan_info()
+    c = I.rx_ry_rz_cz_ladder(5, 1)
+    for make in (lambda: B.qsv_plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs),
+                 lambda: B.qsv_plan_multi([(c.n_qubits, c.gates, c.n_weights, c.n_inputs)] * 2)):
+        h = make()
+        assert L.qsv_plan_get_info(h, ctypes.byref(info)) == 0
+        B.qsv_plan_destroy(h)
+        assert L.qsv_plan_get_info(h, ctypes.byref(info)) == -8
+        assert "destroyed" in B.qsv_last_error()
+        assert L.qsv_workspace_size(h, 2, 0) == 0
+        assert L.qsv_forward(h, fake, fake, 2, fake, fake, big, None) == -8
+        assert L.qsv_forward_expval(h, fake, fake, 2, fake, fake, fake, big, None) == -8
+        assert L.qsv_forward_expval_noalloc(h, fake, fake, 2, fake, fake, None) == -8
+        assert L.qsv_expval(h, fake, 2, fake, fake, big, None) == -8
+        assert L.qsv_backward(h, fake, fake, 2, fake, fake, fake, big, fake, fake, None) == -8
+        assert L.qsv_state_offset(h, 0) == -8
+        assert L.qsv_plan_estimate(h, 2, 1.0, 1.0, 1.0, ctypes.byref(ctypes.c_double())) == -8
+        L.qsv_plan_destroy(h)  # second destroy: ignored
+    # a pointer that never was a plan or a graph (it points at a ctypes buffer)
+    junk = ctypes.create_string_buffer(4096)
+    assert L.qsv_plan_get_info(ctypes.addressof(junk), ctypes.byref(info)) == -8
+    L.qsv_plan_destroy(ctypes.addressof(junk))
+    assert L.qsv_graph_launch(ctypes.addressof(junk), None) == -8
+    L.qsv_graph_destroy(ctypes.addressof(junk))
+    assert L.qsv_graph_launch(None, None) == -8
+
+
 def test_launch_shapes_beyond_hip_grid_limits_are_rejected(lib):
     """A tiled pass launches one block per tile; with small tiles on a large
     state the grid would exceed HIP's 2^32 threads per dimension, which must
