@@ -6,7 +6,12 @@ import numpy as np
 AMP_TOL = 1e-5      # max-abs on amplitudes
 EXP_TOL = 1e-5      # max-abs on <Z_i>
 GRAD_TOL = 1e-4     # relative on gradients (normwise and per entry with a floor)
-GRAD_FLOOR = 1e-1   # per-entry floor, as a fraction of the largest |g*|
+# Per-entry floor, as a fraction of the largest |g*|: the worst per-entry
+# error over every GPU gradient test needs a floor of 1.65e-2 (28-qubit ring,
+# table-driven kernels); 3.5e-2 leaves more than 2x margin. The error comes
+# from float32 amplitude arithmetic over the adjoint sweep: summing the
+# gradient components in float64 instead of float32 changes it by < 1%.
+GRAD_FLOOR = 3.5e-2
 
 
 # Worst per-entry error seen by grad_close in this session, as the smallest
