@@ -572,7 +572,14 @@ private:
         o_ << "  const int t = threadIdx.x;\n";
         o_ << "  const int q4_ = t & 3; const bool lo4_ = q4_ < 2, im4_ = q4_ & 1; (void)lo4_; (void)im4_;\n";
         if (guard_) o_ << "  const bool act = t < " << T_ << ";\n";
-        o_ << "  const unsigned tile = blockIdx.x;\n"
+        // Workgroups are dealt to the chip's 8 XCDs in turn (workgroup i to XCD
+        // i mod 8), each with its own L2. When the tile count divides by 8, XCD x
+        // takes the contiguous tile range [x n/8, (x+1) n/8): the tiles one XCD
+        // holds at a time are then neighbours in the state (adjacent runs of the
+        // lowest out-of-tile bits), not tiles 8 apart. 28 qubits: 54.2 -> 51.7 ms
+        // per step; neutral on the ALU-bound passes.
+        o_ << "  const unsigned tile = (gridDim.x & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (gridDim.x >> 3) + "
+              "(blockIdx.x >> 3);\n"
            << "  const int b = (int)(tile >> " << tb << ");\n"
            << "  const int tis = (int)(tile & " << hex((1u << tb) - 1) << ");\n";
         {

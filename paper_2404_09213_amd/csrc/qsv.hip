@@ -99,6 +99,41 @@ __device__ __forceinline__ M2T<Cplx<R>> load_m2(const R* p) {
     return m;
 }
 
+// Two adjacent amplitudes (index i, i + 1; i even) as one streaming access:
+// 16 bytes for complex64, two 16-byte accesses for complex128. `vec` false
+// (an array that is only 8-byte aligned) falls back to one access each.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_pair(const float2* p, bool vec, float2& a, float2& b) {
+    if (vec) {
+        const f4v v = __builtin_nontemporal_load((const f4v*)p);
+        a = make_float2(v.x, v.y);
+        b = make_float2(v.z, v.w);
+    } else {
+        a = p[0];
+        b = p[1];
+    }
+}
+__device__ __forceinline__ void load_pair(const double2* p, bool vec, double2& a, double2& b) {
+    const d2v u = __builtin_nontemporal_load((const d2v*)p), v = __builtin_nontemporal_load((const d2v*)p + 1);
+    a = make_double2(u.x, u.y);
+    b = make_double2(v.x, v.y);
+    (void)vec;  // double2 arrays are 16-byte aligned
+}
+__device__ __forceinline__ void store_pair(float2* p, bool vec, float2 a, float2 b) {
+    if (vec) {
+        __builtin_nontemporal_store(f4v{a.x, a.y, b.x, b.y}, (f4v*)p);
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+__device__ __forceinline__ void store_pair(double2* p, bool vec, double2 a, double2 b) {
+    __builtin_nontemporal_store(d2v{a.x, a.y}, (d2v*)p);
+    __builtin_nontemporal_store(d2v{b.x, b.y}, (d2v*)p + 1);
+    (void)vec;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -190,8 +225,12 @@ __global__ void k_coef(const DGate* __restrict__ gates, const DRecipe* __restric
 
 // ----------------------------------------------------------------------------
 // product-state init: amp(idx) = prod_q v_q[bit_q(idx)], v_q = column 0 of the
-// prefix matrix of qubit q. Work split: chunk of 2^cb amplitudes per block,
-// lanes over the low tb bits, a loop over the next jb bits.
+// prefix matrix of qubit q. One block per chunk of 2^cb amplitudes (cb =
+// min(W, 12)) and sample: the block first tabulates, in LDS, the products
+// over the chunk's low h bits (lo, 2^h entries) and over its other cb - h
+// bits times the chunk's constant factor from the bits above cb (hi), so
+// every amplitude is one complex product lo[.] hi[.], written as 16-byte
+// streaming pairs.
 // ----------------------------------------------------------------------------
 template <class R>
 __device__ __forceinline__ Cplx<R> prefix_v(const R* mats, const int32_t* pm, int q, int bit,
@@ -204,54 +243,68 @@ template <class V>
 __global__ __launch_bounds__(256) void k_init(V* __restrict__ state, int W,
                                               const int32_t* __restrict__ pm,
                                               const Real<V>* __restrict__ mats, int n_shared,
-                                              int n_ps) {
-    const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
+                                              int n_ps, int vec) {
+    __shared__ V lo[64], hi[64];
+    const int cb = min(W, 12), h = cb / 2, hb = cb - h;
     const int t = threadIdx.x;
-    if (t >= (1 << tb)) return;
     const int b = blockIdx.y;
     const int64_t chunk = blockIdx.x;
-    V P = mkc(Real<V>(1), Real<V>(0));
-    for (int s = 0; s < tb; ++s) P = cmul(P, prefix_v(mats, pm, W - 1 - s, (t >> s) & 1, b, n_shared, n_ps));
-    for (int s = cb; s < W; ++s)
-        P = cmul(P, prefix_v(mats, pm, W - 1 - s, (int)((chunk >> (s - cb)) & 1), b, n_shared, n_ps));
-    V* st = state + ((size_t)b << W);
-    for (int j = 0; j < (1 << jb); ++j) {
-        V Q = P;
-        for (int s = tb; s < cb; ++s)
-            Q = cmul(Q, prefix_v(mats, pm, W - 1 - s, (j >> (s - tb)) & 1, b, n_shared, n_ps));
-        st[(chunk << cb) | ((int64_t)j << tb) | t] = Q;
+    if (t < (1 << h)) {
+        V P = mkc(Real<V>(1), Real<V>(0));
+        for (int s = 0; s < h; ++s) P = cmul(P, prefix_v(mats, pm, W - 1 - s, (t >> s) & 1, b, n_shared, n_ps));
+        lo[t] = P;
+    } else if (t >= 64 && t < 64 + (1 << hb)) {
+        const int k = t - 64;
+        V P = mkc(Real<V>(1), Real<V>(0));
+        for (int s = h; s < cb; ++s)
+            P = cmul(P, prefix_v(mats, pm, W - 1 - s, (k >> (s - h)) & 1, b, n_shared, n_ps));
+        for (int s = cb; s < W; ++s)
+            P = cmul(P, prefix_v(mats, pm, W - 1 - s, (int)((chunk >> (s - cb)) & 1), b, n_shared, n_ps));
+        hi[k] = P;
     }
+    __syncthreads();
+    V* st = state + ((size_t)b << W) + ((size_t)chunk << cb);
+    const int lm = (1 << h) - 1;
+    for (int i = 2 * t; i < (1 << cb); i += 512)
+        store_pair(st + i, vec, cmul(lo[i & lm], hi[i >> h]), cmul(lo[(i + 1) & lm], hi[(i + 1) >> h]));
 }
 
 // ----------------------------------------------------------------------------
 // readout
 // ----------------------------------------------------------------------------
+// <Z_i> partials of one chunk of 2^cb amplitudes (cb = min(W, 12)) of one
+// sample: thread t reads the pairs (2i, 2i + 1), i = t + 2^tb j, so bit 0
+// sits in the pair, bits 1..tb come from t and the bits above from j.
+// Per-thread float32 sums over at most 16 amplitudes, float64 above.
 template <class V>
 __global__ __launch_bounds__(256) void k_expval_part(const V* __restrict__ state, int W,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, int vec) {
     using R = Real<V>;
-    __shared__ double red[4][14];
-    const int cb = min(W, 12), tb = min(cb, 8), jb = cb - tb;
+    __shared__ double red[4][13];
+    const int cb = min(W, 12), tb = min(cb - 1, 8), jb = cb - 1 - tb;
     const int t = threadIdx.x;
     const int b = blockIdx.y;
     const int64_t chunk = blockIdx.x;
     const int64_t nchunk = gridDim.x;
-    const V* st = state + ((size_t)b << W);
-    R T = 0, S[4] = {0, 0, 0, 0};
+    const V* st = state + ((size_t)b << W) + ((size_t)chunk << cb);
+    R T = 0, S0 = 0, S[3] = {0, 0, 0};
     if (t < (1 << tb)) {
         for (int j = 0; j < (1 << jb); ++j) {
-            const V a = st[(chunk << cb) | ((int64_t)j << tb) | t];
-            const R p = a.x * a.x + a.y * a.y;
-            T += p;
+            V a0, a1;
+            load_pair(st + 2 * (((size_t)j << tb) | t), vec != 0, a0, a1);
+            const R p0 = a0.x * a0.x + a0.y * a0.y, p1 = a1.x * a1.x + a1.y * a1.y;
+            T += p0 + p1;
+            S0 += p1;
             for (int i = 0; i < jb; ++i)
-                if ((j >> i) & 1) S[i] += p;
+                if ((j >> i) & 1) S[i] += p0 + p1;
         }
     }
-    // values: [0] total, [1..4] j-bit sums, [5..12] thread-bit weighted totals
+    // values: [0] total, [1] bit-0 sum, [2..4] j-bit sums, [5..12] thread-bit weighted totals
     double v[13];
     v[0] = T;
-    for (int i = 0; i < 4; ++i) v[1 + i] = S[i];
-    for (int s = 0; s < 8; ++s) v[5 + s] = ((t >> s) & 1) ? (double)T : 0.0;
+    v[1] = S0;
+    for (int i = 0; i < 3; ++i) v[2 + i] = S[i];
+    for (int k = 0; k < 8; ++k) v[5 + k] = ((t >> k) & 1) ? (double)T : 0.0;
     const int wave = t >> 6, lane = t & 63;
     for (int k = 0; k < 13; ++k) {
         const double r = wave_sum(v[k]);
@@ -260,12 +313,13 @@ __global__ __launch_bounds__(256) void k_expval_part(const V* __restrict__ state
     __syncthreads();
     if (t < W) {
         auto tot = [&](int k) { return red[0][k] + red[1][k] + red[2][k] + red[3][k]; };
-        const int s = W - 1 - t;  // qubit t has shift s
+        const int sh = W - 1 - t;  // qubit t is index bit sh
         const double Tsum = tot(0);
         double e;
-        if (s < tb) e = Tsum - 2.0 * tot(5 + s);
-        else if (s < cb) e = Tsum - 2.0 * tot(1 + (s - tb));
-        else e = ((chunk >> (s - cb)) & 1) ? -Tsum : Tsum;
+        if (sh == 0) e = Tsum - 2.0 * tot(1);
+        else if (sh <= tb) e = Tsum - 2.0 * tot(5 + sh - 1);
+        else if (sh < cb) e = Tsum - 2.0 * tot(2 + sh - 1 - tb);
+        else e = ((chunk >> (sh - cb)) & 1) ? -Tsum : Tsum;
         part[((size_t)b * nchunk + chunk) * W + t] = e;
     }
 }
@@ -509,7 +563,6 @@ __global__ __launch_bounds__(256) void k_pg_apply(V* __restrict__ state, int W, 
 //                fixed bits are all 1 negated, and everything written back with
 //                full 16-byte stores.
 enum { PG_SCALAR = 0, PG_VEC_PAIRS = 1, PG_VEC_ADJ = 2, PG_VEC_SWEEP = 3 };
-typedef float f4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f4v ntl4(const float2* p) { return __builtin_nontemporal_load((const f4v*)p); }
 // cached load: for a pair whose two halves share a cache line (target bit <= 3),
 // where a streaming load of the second half would fetch the line again
@@ -580,23 +633,51 @@ __global__ __launch_bounds__(256) void k_pg_apply_vec(float2* __restrict__ state
     nts4(state + i1, cat2(y0, y1));
 }
 
-// lambda = D psi_N with D(idx) = sum_i g[b,i] (1 - 2 bit_i(idx)); psi copied to the workspace.
+// lambda = D psi_N with D(idx) = sum_i g[b,i] (1 - 2 bit_i(idx)) = G - 2 sum over
+// the set bits, psi_N copied to the workspace. One block per chunk of 2^cb
+// amplitudes (cb = min(W, 12)) and sample; the block tabulates the set-bit
+// sums of its low h bits (lo) and of its other bits (hi, including the
+// chunk's bits above cb) in float64, then streams 16-byte pairs.
 template <class V>
 __global__ __launch_bounds__(256) void k_adj_init(const V* __restrict__ psiN,
                                                   V* __restrict__ psi, V* __restrict__ lam,
-                                                  int W, int64_t B, const double* __restrict__ g) {
-    const int64_t it = block_1d() * 256 + threadIdx.x;
-    if (it >= (B << W)) return;
-    const int64_t b = it >> W;
-    const int64_t idx = it & ((int64_t(1) << W) - 1);
-    double d = 0.0;
-    for (int i = 0; i < W; ++i) {
-        const double gi = g[b * W + i];
-        d += ((idx >> (W - 1 - i)) & 1) ? -gi : gi;
+                                                  int W, const double* __restrict__ g, int vec) {
+    __shared__ double gs[32], lo[64], hi[64], G;
+    const int cb = min(W, 12), h = cb / 2, hb = cb - h;
+    const int t = threadIdx.x;
+    const int b = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    if (t < W) gs[t] = g[(size_t)b * W + t];
+    __syncthreads();
+    if (t < (1 << h)) {
+        double d = 0.0;
+        for (int s = 0; s < h; ++s)
+            if ((t >> s) & 1) d += gs[W - 1 - s];
+        lo[t] = d;
+    } else if (t >= 64 && t < 64 + (1 << hb)) {
+        const int k = t - 64;
+        double d = 0.0;
+        for (int s = h; s < cb; ++s)
+            if ((k >> (s - h)) & 1) d += gs[W - 1 - s];
+        for (int s = cb; s < W; ++s)
+            if ((chunk >> (s - cb)) & 1) d += gs[W - 1 - s];
+        hi[k] = d;
+    } else if (t == 128) {
+        double d = 0.0;
+        for (int i = 0; i < W; ++i) d += gs[i];
+        G = d;
     }
-    const V a = psiN[it];
-    psi[it] = a;
-    lam[it] = mkc((Real<V>)d * a.x, (Real<V>)d * a.y);
+    __syncthreads();
+    const size_t base = ((size_t)b << W) + ((size_t)chunk << cb);
+    const int lm = (1 << h) - 1;
+    for (int i = 2 * t; i < (1 << cb); i += 512) {
+        V a0, a1;
+        load_pair(psiN + base + i, vec != 0, a0, a1);
+        const Real<V> d0 = (Real<V>)(G - 2.0 * (lo[i & lm] + hi[i >> h]));
+        const Real<V> d1 = (Real<V>)(G - 2.0 * (lo[(i + 1) & lm] + hi[(i + 1) >> h]));
+        store_pair(psi + base + i, true, a0, a1);
+        store_pair(lam + base + i, true, mkc(d0 * a0.x, d0 * a0.y), mkc(d1 * a1.x, d1 * a1.y));
+    }
 }
 
 // Plain-method backward step for one gate: gradient partial at psi_k, lambda_k,
@@ -1764,12 +1845,13 @@ int run_init(const qsv_plan_t* p, DeviceTables* T, const float* mats, int64_t B,
     const int cb = std::min(p->W, 12);
     dim3 grid((unsigned)(int64_t(1) << (p->W - cb)), (unsigned)B);
     hipEvent_t ev = prof_begin(p, s);
+    const int vec = ((uintptr_t)st & 15) == 0;
     if (c128(p))
         hipLaunchKernelGGL(k_init<double2>, grid, dim3(256), 0, s, (double2*)st, p->W, T->prefix_mat,
-                           (const double*)mats, p->n_shared_mats, p->n_ps_mats);
+                           (const double*)mats, p->n_shared_mats, p->n_ps_mats, vec);
     else
         hipLaunchKernelGGL(k_init<float2>, grid, dim3(256), 0, s, st, p->W, T->prefix_mat, mats,
-                           p->n_shared_mats, p->n_ps_mats);
+                           p->n_shared_mats, p->n_ps_mats, vec);
     const double amps = (double)B * (double)(int64_t(1) << p->W);
     prof_end(p, s, ev, K_INIT, (double)amp_size(p) * amps, 0.0);
     HIP_TRY(hipGetLastError());
@@ -2389,12 +2471,13 @@ int qsv_expval(const qsv_plan_t* p, const void* d_state, int64_t B, double* out,
     double* part = (double*)ws;
     const double amps = (double)B * (double)(int64_t(1) << p->W);
     hipEvent_t ev = prof_begin(p, s);
+    const int vec = ((uintptr_t)d_state & 15) == 0;
     if (c128(p))
         hipLaunchKernelGGL(k_expval_part<double2>, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
-                           (const double2*)d_state, p->W, part);
+                           (const double2*)d_state, p->W, part, vec);
     else
         hipLaunchKernelGGL(k_expval_part<float2>, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s,
-                           (const float2*)d_state, p->W, part);
+                           (const float2*)d_state, p->W, part, vec);
     prof_end(p, s, ev, K_EXPVAL_PART, (double)amp_size(p) * amps, 3.0 * amps);
     ev = prof_begin(p, s);
     hipLaunchKernelGGL(k_expval_final, dim3((unsigned)p->W, (unsigned)B), dim3(256), 0, s,
@@ -2456,14 +2539,15 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
         }
         prof_end(p, s, ev, K_MULTI_BWD, bytes, flops);
     } else if (p->opts.method == QSV_METHOD_PER_GATE) {
-        const int64_t n = B << W;
+        const dim3 grid((unsigned)expval_nchunk(p), (unsigned)B);  // chunks of 2^min(W, 12) amplitudes
+        const int vec = ((uintptr_t)d_state & 15) == 0;
         hipEvent_t ev = prof_begin(p, s);
         if (c128(p))
-            hipLaunchKernelGGL(k_adj_init<double2>, grid_1d((n + 255) / 256), dim3(256), 0, s,
-                               (const double2*)d_state, (double2*)psi, (double2*)lam, W, B, gout);
+            hipLaunchKernelGGL(k_adj_init<double2>, grid, dim3(256), 0, s,
+                               (const double2*)d_state, (double2*)psi, (double2*)lam, W, gout, vec);
         else
-            hipLaunchKernelGGL(k_adj_init<float2>, grid_1d((n + 255) / 256), dim3(256), 0, s,
-                               (const float2*)d_state, psi, lam, W, B, gout);
+            hipLaunchKernelGGL(k_adj_init<float2>, grid, dim3(256), 0, s,
+                               (const float2*)d_state, psi, lam, W, gout, vec);
         prof_end(p, s, ev, K_ADJ_INIT, 3.0 * (double)amp_size(p) * amps, 2.0 * W * amps);
         for (size_t i = 0; i < p->pg_bwd.size(); ++i) {
             const PGate& pg = p->pg_bwd[i];
