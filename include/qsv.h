@@ -206,10 +206,15 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
  * executed in parallel); the call is this library's addition for batches of
  * unrelated circuits. Every circuit is split and scheduled as by qsv_plan
  * (fused method, table-driven kernels, tile_qubits <= 12). qsv_forward and
- * qsv_backward then run pass r of EVERY circuit in one launch ("round r"),
- * one workgroup per (circuit, tile); a circuit's next pass is in the next
- * round, so the number of launches per direction is the largest pass count of
- * any circuit, not the number of circuits. No workgroup waits on another.
+ * qsv_backward then run every pass of every circuit in ONE persistent launch
+ * per direction: workgroups take (circuit, pass, tile) items from a queue in
+ * the order of qsv_plan_multi_items, and an item of pass r waits until all
+ * tiles of pass r - 1 of its circuit are done (counters in the workspace,
+ * agent-scope atomics). Each wait is bounded (QSV_MULTI_WAIT_MS, default
+ * 1000 ms): past it the launch stops and the results are poisoned with NaN
+ * (amplitude 0 of every circuit after a forward, every gradient after a
+ * backward). With QSV_MULTI_LAUNCH=rounds the calls instead launch pass r of
+ * every circuit as one launch per round, with no waiting between workgroups.
  * Layouts with the plan (c = circuit, prefix sums over earlier circuits):
  *   weights:      concatenation of every circuit's weights;
  *   inputs:       batch x (sum of n_inputs), circuit c's columns after c-1's;
@@ -232,6 +237,19 @@ int qsv_plan_circuit_offsets(const qsv_plan_t* plan, int32_t circuit, int64_t* a
  * negative QSV_ERR_* code (QSV_ERR_HANDLE, QSV_ERR_ARG for an index out of
  * range). */
 int64_t qsv_state_offset(const qsv_plan_t* plan, int32_t circuit);
+
+/*
+ * Work list of a multi-circuit plan at this batch size, in the order one
+ * forward (which = 0) or backward (which = 1) launch processes it: item i is
+ * (circuit, pass, tile) at items[3i .. 3i+2]. Pass r of every circuit comes
+ * after all tiles of its pass r - 1 (the list goes round by round, larger
+ * circuits first within a round); a persistent launch takes items in this
+ * order and starts an item of pass r once every tile of pass r - 1 of its
+ * circuit is done. Copies at most max_items items (items may be NULL) and
+ * stores the total count in *n_items. Host only.
+ */
+int qsv_plan_multi_items(const qsv_plan_t* plan, int64_t batch, int32_t which, int32_t* items,
+                         int64_t max_items, int64_t* n_items);
 
 /* Release a plan and its device tables. NULL, an already destroyed plan and
  * any pointer that is not a live plan are ignored: handles are checked

@@ -73,7 +73,7 @@ class qsv_kernel_stat(ctypes.Structure):
 
 
 EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets", "qsv_state_offset",
-           "qsv_plan_destroy", "qsv_workspace_size",
+           "qsv_plan_multi_items", "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_forward_expval_noalloc",
            "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
@@ -114,6 +114,8 @@ def lib():
         L.qsv_plan_circuit_offsets.restype = ctypes.c_int
         L.qsv_state_offset.argtypes = [vp, i32]
         L.qsv_state_offset.restype = i64
+        L.qsv_plan_multi_items.argtypes = [vp, i64, i32, vp, i64, ctypes.POINTER(i64)]
+        L.qsv_plan_multi_items.restype = ctypes.c_int
         L.qsv_plan_destroy.argtypes = [vp]
         L.qsv_plan_destroy.restype = None
         L.qsv_workspace_size.argtypes = [vp, i64, i32]
@@ -222,6 +224,17 @@ def qsv_state_offset(h, circuit):
     if v < 0:
         raise QsvError(v, lib().qsv_last_error().decode())
     return v
+
+
+def qsv_plan_multi_items(h, batch, which):
+    """Work list of a multi-circuit plan: int32 array (n_items, 3) of (circuit, pass, tile)."""
+    n = ctypes.c_int64()
+    _check(lib().qsv_plan_multi_items(h, int(batch), int(which), None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, 3), dtype=np.int32)
+    if n.value:
+        _check(lib().qsv_plan_multi_items(h, int(batch), int(which), out.ctypes.data_as(ctypes.c_void_p), n.value,
+                                          ctypes.byref(n)))
+    return out
 
 
 def qsv_plan_destroy(h):

@@ -1,8 +1,15 @@
-"""Many circuits in one plan (uneven batch: pass r of every circuit in one launch).
+"""Many circuits in one plan (uneven batch: every pass of every circuit in one
+persistent launch per direction, or one launch per round of passes).
 
 Each circuit's slice of the combined state, expectations and gradients must
-equal the oracle run on that circuit alone.
+equal the oracle run on that circuit alone; both launch forms must agree bit
+for bit; and the work list's order must let a persistent launch of any size
+drain without deadlock (checked by simulating the claim-and-wait protocol on
+the host).
 """
+import heapq
+import os
+
 import numpy as np
 import pytest
 
@@ -82,6 +89,79 @@ def test_uneven_set_shape():
     assert mp.state_len == sum(1 << n for n in ns)
 
 
+def _check_order(items, ntiles):
+    """Every (circuit, pass) has all its tiles once, and every item of pass r
+    comes after all tiles of pass r - 1 of its circuit."""
+    last = {}
+    seen = {}
+    for pos, (c, r, t) in enumerate(items):
+        key = (int(c), int(r))
+        seen.setdefault(key, set()).add(int(t))
+        last[key] = pos
+    for (c, r), tiles in seen.items():
+        assert tiles == set(range(ntiles[c])), (c, r)
+        assert r == 0 or (c, r - 1) in seen
+    first = {}
+    for pos, (c, r, t) in enumerate(items):
+        first.setdefault((int(c), int(r)), pos)
+    for (c, r), pos in first.items():
+        if r:
+            assert last[(c, r - 1)] < pos, (c, r)
+
+
+def _simulate(items, ntiles, workers, seed):
+    """Discrete-event run of the persistent launch's protocol: each worker
+    claims the next item in list order, waits (without giving the item up)
+    until all tiles of the circuit's previous pass are done, works for a
+    random time, then counts its tile. Returns False on deadlock (every live
+    worker waiting, nothing running)."""
+    rng = np.random.default_rng(seed)
+    done = {}
+    head = 0
+    clock = 0.0
+    running = []            # (finish time, worker, circuit)
+    waiting = {}            # worker -> item
+    idle = list(range(workers))
+    n = len(items)
+    while True:
+        while idle and head < n:
+            w = idle.pop()
+            waiting[w] = items[head]
+            head += 1
+        for w, (c, r, t) in list(waiting.items()):
+            if done.get(int(c), 0) >= int(r) * ntiles[int(c)]:
+                del waiting[w]
+                heapq.heappush(running, (clock + rng.exponential(1.0), w, int(c)))
+        if not running:
+            return not waiting and head == n
+        clock, w, c = heapq.heappop(running)
+        done[c] = done.get(c, 0) + 1
+        idle.append(w)
+
+
+@pytest.mark.parametrize("batch", [1, 3])
+def test_multi_work_list_drains_in_any_persistent_launch(batch):
+    cs = _mixed_set(11, 9, 9, 16)  # circuits above 12 qubits need several passes
+    mp = B.MultiPlan(cs)
+    tq = B.qsv_default_opts().tile_qubits
+    ntiles = [batch << (c.n_qubits - min(tq, c.n_qubits)) for c in cs]
+    for which in (0, 1):
+        items = B.qsv_plan_multi_items(mp.handle, batch, which)
+        assert items[:, 1].max() >= 1  # dependencies to wait for
+        _check_order(items, ntiles)
+        for workers in (1, 2, 7, 64, 1000):
+            assert _simulate(items, ntiles, workers, seed=workers + which)
+        # a list in the wrong order can deadlock: the check is not vacuous
+        assert not _simulate(items[::-1], ntiles, 1, seed=0)
+    big = I.uneven_set(512)
+    mp = B.MultiPlan(big)
+    ntiles = [batch << (c.n_qubits - min(tq, c.n_qubits)) for c in big]
+    for which in (0, 1):
+        items = B.qsv_plan_multi_items(mp.handle, batch, which)
+        _check_order(items, ntiles)
+        assert _simulate(items, ntiles, 1024, seed=5)
+
+
 # -- GPU parity ---------------------------------------------------------------------------
 
 def _run_multi(cs, batch, seed, orc, check_ids=None, **opts):
@@ -151,3 +231,32 @@ def test_multi_uneven_512_sampled(orc):
     rng = np.random.default_rng(1004)
     ids = sorted(set(rng.choice(512, 6, replace=False).tolist()) | {int(np.argmax([c.n_qubits for c in cs]))})
     _run_multi(cs, 1, 1004, orc, check_ids=ids)
+
+
+@pytest.mark.gpu
+def test_multi_persistent_matches_rounds():
+    """One persistent launch per direction and one launch per round run the
+    same tile arithmetic: states, expectations and gradients bit for bit."""
+    import torch
+    dev = torch.device("cuda:0")
+    cs = _mixed_set(21, 12, 4, 14)
+    batch = 2
+    w, x, _, _ = _draw(cs, batch, 21)
+    mp = B.MultiPlan(cs)
+    g = torch.from_numpy(np.random.default_rng(21).uniform(-1, 1, size=(batch, mp.n_out))).to(dev)
+    wt = torch.from_numpy(w).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    out = {}
+    for mode in ("rounds", "persistent"):
+        os.environ["QSV_MULTI_LAUNCH"] = mode
+        try:
+            print(f"[multi] launch form {mode}", flush=True)
+            st, E = mp.forward_expval(wt, xt, batch)
+            gw, gx = mp.backward(wt, xt, st, g)
+            torch.cuda.synchronize()
+            out[mode] = (st.clone(), E.clone(), gw.clone(), gx.clone())
+        finally:
+            del os.environ["QSV_MULTI_LAUNCH"]
+    for a, b in zip(out["rounds"], out["persistent"]):
+        assert torch.equal(a, b)
+    assert torch.isfinite(out["persistent"][1]).all()
