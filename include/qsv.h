@@ -206,15 +206,14 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
  * executed in parallel); the call is this library's addition for batches of
  * unrelated circuits. Every circuit is split and scheduled as by qsv_plan
  * (fused method, table-driven kernels, tile_qubits <= 12). qsv_forward and
- * qsv_backward then run every pass of every circuit in ONE persistent launch
- * per direction: workgroups take (circuit, pass, tile) items from a queue in
- * the order of qsv_plan_multi_items, and an item of pass r waits until all
- * tiles of pass r - 1 of its circuit are done (counters in the workspace,
- * agent-scope atomics). Each wait is bounded (QSV_MULTI_WAIT_MS, default
- * 1000 ms): past it the launch stops and the results are poisoned with NaN
- * (amplitude 0 of every circuit after a forward, every gradient after a
- * backward). With QSV_MULTI_LAUNCH=rounds the calls instead launch pass r of
- * every circuit as one launch per round, with no waiting between workgroups.
+ * qsv_backward then run pass r of EVERY circuit in one launch ("round r"),
+ * one workgroup per (circuit, tile) in the order of qsv_plan_multi_items; a
+ * circuit's next pass is in the next round, so the number of launches per
+ * direction is the largest pass count of any circuit, not the number of
+ * circuits. No workgroup waits on another. (A single persistent launch per
+ * direction that walks the same list, each item waiting for its circuit's
+ * previous pass, stopped making progress on its first device run; it is not
+ * used.)
  * Layouts with the plan (c = circuit, prefix sums over earlier circuits):
  *   weights:      concatenation of every circuit's weights;
  *   inputs:       batch x (sum of n_inputs), circuit c's columns after c-1's;
@@ -243,10 +242,11 @@ int64_t qsv_state_offset(const qsv_plan_t* plan, int32_t circuit);
  * forward (which = 0) or backward (which = 1) launch processes it: item i is
  * (circuit, pass, tile) at items[3i .. 3i+2]. Pass r of every circuit comes
  * after all tiles of its pass r - 1 (the list goes round by round, larger
- * circuits first within a round); a persistent launch takes items in this
- * order and starts an item of pass r once every tile of pass r - 1 of its
- * circuit is done. Copies at most max_items items (items may be NULL) and
- * stores the total count in *n_items. Host only.
+ * circuits first within a round); a persistent launch taking items in this
+ * order would start an item of pass r once every tile of pass r - 1 of its
+ * circuit is done; the round launches run round r as one launch. Copies at
+ * most max_items items (items may be NULL) and stores the total count in
+ * *n_items. Host only.
  */
 int qsv_plan_multi_items(const qsv_plan_t* plan, int64_t batch, int32_t which, int32_t* items,
                          int64_t max_items, int64_t* n_items);

@@ -351,8 +351,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
                                                      const int32_t* __restrict__ nchv,
                                                      double* __restrict__ gw,
                                                      double* __restrict__ gx,
-                                                     const float* __restrict__ weights, int remap,
-                                                     const int* __restrict__ fail) {
+                                                     const float* __restrict__ weights, int remap) {
     __shared__ double red[256];
     const int t = threadIdx.x;
     const int o = blockIdx.x;  // output index: weights first, then (b, input)
@@ -390,7 +389,6 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
         __syncthreads();
     }
     if (t == 0) {
-        if (fail && *fail) red[0] = __longlong_as_double(0x7ff8000000000000ll);  // aborted multi-circuit launch
         if (o < n_weights) {
             double f = 1.0;
             if (remap) {  // d(pi tanh w)/dw
@@ -1498,134 +1496,6 @@ __global__ __launch_bounds__(256) void k_multi_bwd(
                   psi + off, lam + off, gout + (size_t)b * Wtot + c.e0, c.W, B, b, tis, part, pu, lds);
 }
 
-// ----------------------------------------------------------------------------
-// many circuits, one persistent launch per direction
-// ----------------------------------------------------------------------------
-// Workgroups take items in work-list order from a queue head; an item of pass
-// r > 0 first waits until every tile of pass r - 1 of its circuit is done
-// (a per-circuit count of finished tiles). A workgroup claims an item only
-// while it runs and never waits on a later item, and every item's
-// predecessors come earlier in the list, so the earliest unfinished item can
-// always proceed: the launch drains whatever its size. Visibility across the
-// chip's XCDs (each has its own L2): the producer's tile stores reach its L2
-// before the workgroup barrier, its thread 0 then releases at agent scope
-// (writing the L2 back) before the agent-scope count increment; the waiter
-// polls the count with agent-scope loads and acquires at agent scope before
-// the barrier that releases its threads to read. Every wait is bounded by
-// wall-clock time: past the limit the waiter raises the abort flag, every
-// workgroup stops at its next claim or wait, and the host-visible results are
-// poisoned with NaN (k_multi_poison, k_grad_reduce).
-// Sync area (caller's workspace): [0] queue head, [1] abort flag,
-// [kSyncDone0 + c] finished tiles of circuit c.
-constexpr int kSyncDone0 = 64;
-
-__global__ void k_multi_sync_clear(int* __restrict__ sync, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) sync[i] = 0;
-}
-
-// thread 0 of a workgroup: wait until *cnt >= target (true), or give up on
-// abort / time-out (false, abort raised)
-__device__ bool multi_wait(int* cnt, int target, int* abort, long long ticks) {
-    const long long t0 = wall_clock64();
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (wall_clock64() - t0 > ticks) {
-            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
-}
-
-// thread 0: claim the next item and wait for its predecessors; the result
-// (item index, or -1 to stop) is broadcast through LDS
-__device__ __forceinline__ int multi_next(const DCirc* __restrict__ C, const DItem* __restrict__ Q, int n_items,
-                                          int* __restrict__ sync, long long ticks, int B, int* slot) {
-    if (threadIdx.x == 0) {
-        int i = -1;
-        if (!__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            const int k = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k < n_items) {
-                const DItem I = Q[k];
-                const DCirc& c = C[I.c];
-                const int need = I.pass * (B << (c.W - c.m));
-                i = (I.pass == 0 || multi_wait(&sync[kSyncDone0 + I.c], need, &sync[1], ticks)) ? k : -1;
-            }
-        }
-        *slot = i;
-    }
-    __syncthreads();
-    return *slot;
-}
-
-// publish one finished tile: every wave releases its own stores at agent
-// scope (a plain workgroup barrier does not wait for them), then, after the
-// barrier, thread 0 counts the tile
-__device__ __forceinline__ void multi_done(int* __restrict__ sync, int c) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(&sync[kSyncDone0 + c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__global__ __launch_bounds__(256) void k_multi_fwd_all(
-    const DCirc* __restrict__ C, const DItem* __restrict__ Q, int n_items,
-    const DPass* __restrict__ passes, const DStage* __restrict__ S, const DOp* __restrict__ O,
-    const DTerm* __restrict__ Tm, const float* __restrict__ mats, int n_shared, int n_ps,
-    float2* __restrict__ state, int64_t row, int B, int* __restrict__ sync, long long ticks) {
-    extern __shared__ float2 lds[];
-    __shared__ int slot;
-    for (;;) {
-        const int k = multi_next(C, Q, n_items, sync, ticks, B, &slot);
-        if (k < 0) break;
-        const DItem I = Q[k];
-        const DCirc& c = C[I.c];
-        const int tbits = c.W - c.m;
-        const int b = I.tile >> tbits;
-        const int64_t tis = I.tile & ((1 << tbits) - 1);
-        pass_fwd_tile(passes + c.fwd0 + I.pass, S, O, Tm, mats, n_shared, n_ps,
-                      state + (size_t)b * row + c.amp0, c.W, b, tis, lds);
-        multi_done(sync, I.c);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_multi_bwd_all(
-    const DCirc* __restrict__ C, const DItem* __restrict__ Q, int n_items,
-    const DPass* __restrict__ passes, const DStage* __restrict__ S, const DOp* __restrict__ O,
-    const DTerm* __restrict__ Tm, const DGOut* __restrict__ gouts,
-    const float* __restrict__ mats, int n_shared, int n_ps, const float2* __restrict__ psiN,
-    float2* __restrict__ psi, float2* __restrict__ lam, const double* __restrict__ gout, int Wtot,
-    int64_t row, int B, double* __restrict__ part, const int64_t* __restrict__ pu, int* __restrict__ sync,
-    long long ticks) {
-    extern __shared__ float2 lds[];
-    __shared__ int slot;
-    for (;;) {
-        const int k = multi_next(C, Q, n_items, sync, ticks, B, &slot);
-        if (k < 0) break;
-        const DItem I = Q[k];
-        const DCirc& c = C[I.c];
-        const int tbits = c.W - c.m;
-        const int b = I.tile >> tbits;
-        const int64_t tis = I.tile & ((1 << tbits) - 1);
-        const size_t off = (size_t)b * row + c.amp0;
-        pass_bwd_tile(passes + c.bwd0 + I.pass, S, O, Tm, gouts, mats, n_shared, n_ps, psiN + off,
-                      psi + off, lam + off, gout + (size_t)b * Wtot + c.e0, c.W, B, b, tis, part, pu, lds);
-        multi_done(sync, I.c);
-    }
-}
-
-// after an aborted forward launch: amplitude 0 of every circuit and sample
-// becomes NaN, so the readout and anything computed from the state show it
-__global__ void k_multi_poison(const int* __restrict__ sync, float2* __restrict__ state, int64_t row,
-                               const DCirc* __restrict__ C, int n_circ, int B) {
-    if (!sync[1]) return;
-    const float nan = __int_as_float(0x7fc00000);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_circ * B; i += gridDim.x * blockDim.x)
-        state[(size_t)(i / n_circ) * row + C[i % n_circ].amp0] = make_float2(nan, nan);
-}
-
 // product-state init of every circuit: grid (sum of per-circuit chunks, B)
 __global__ __launch_bounds__(256) void k_init_multi(const DCirc* __restrict__ C, int n_circ,
                                                     float2* __restrict__ state, int64_t row,
@@ -1917,36 +1787,6 @@ int64_t row_amps(const qsv_plan_t* p) { return p->multi ? p->row : int64_t(1) <<
 
 size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * (size_t)row_amps(p) * amp_size(p); }
 
-// sync area of a persistent multi-circuit launch (queue head, abort flag,
-// per-circuit tile counts), at the end of the forward and backward workspaces
-size_t multi_sync_bytes(const qsv_plan_t* p) {
-    return p->multi ? align256((size_t)(kSyncDone0 + p->circ.size()) * sizeof(int)) : 0;
-}
-
-// Persistent multi-circuit launches (the default) or one launch per round
-// (QSV_MULTI_LAUNCH=rounds); the wait limit of the persistent launches in
-// milliseconds (QSV_MULTI_WAIT_MS, default 1000).
-bool multi_persistent() {
-    const char* e = std::getenv("QSV_MULTI_LAUNCH");
-    return !(e && std::strcmp(e, "rounds") == 0);
-}
-
-// grid of a persistent launch (workgroups that fit on the device at once, at
-// most one per item) and its wait limit in wall-clock ticks
-int multi_launch_shape(const void* kernel, size_t lds, int n_items, unsigned* grid, long long* ticks) {
-    int dev = 0, ncu = 0, per = 0, khz = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, lds));
-    const long long cap = (long long)std::max(per, 1) * std::max(ncu, 1);
-    *grid = (unsigned)std::max(1LL, std::min<long long>(cap, n_items));
-    const char* e = std::getenv("QSV_MULTI_WAIT_MS");
-    const long long ms = e && *e ? std::max(1LL, std::atoll(e)) : 1000LL;
-    *ticks = (long long)std::max(khz, 1) * ms;
-    return QSV_OK;
-}
-
 size_t partial_bytes(const qsv_plan_t* p, int64_t B) {
     return align256((size_t)std::max<int64_t>(p->pu_total, 1) * B * sizeof(double));
 }
@@ -2052,8 +1892,9 @@ int check_batch(const qsv_plan_t* p, int64_t B) {
 // plan at batch B: round r lists every tile of pass r of every circuit that
 // has one, larger circuits first; rounds[r] is round r's first item (and
 // rounds.back() the item count). Every item's predecessors (all tiles of the
-// circuit's previous pass) come earlier in the list, which is what lets one
-// persistent launch walk it in order without deadlock.
+// circuit's previous pass) come earlier in the list: the rounds run it as
+// one launch per round, and a single persistent launch could walk it in
+// order without deadlock (qsv_plan_multi_items exposes it for that check).
 void multi_items(const qsv_plan_t* p, int64_t B, int dir, std::vector<DItem>& items, std::vector<int>& rounds) {
     std::vector<int> order(p->circ.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -2381,12 +2222,12 @@ int qsv_plan_gate_blocks(const qsv_plan_t* p, int32_t* block_of_gate) {
 size_t qsv_workspace_size(const qsv_plan_t* p, int64_t B, int32_t op) {
     if (check_plan(p) || B <= 0) return 0;
     switch (op) {
-    case QSV_OP_FORWARD: return mats_bytes(p, B) + multi_sync_bytes(p);
+    case QSV_OP_FORWARD: return mats_bytes(p, B);
     case QSV_OP_EXPVAL:
         if (p->multi) return align256((size_t)B * p->nchunk_tot * 32 * sizeof(double));
         return align256((size_t)B * expval_nchunk(p) * p->W * sizeof(double));
     case QSV_OP_BACKWARD:
-        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + partial_bytes(p, B) + multi_sync_bytes(p);
+        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + partial_bytes(p, B);
     case QSV_OP_STEP:
         return std::max(qsv_workspace_size(p, B, QSV_OP_BACKWARD), qsv_workspace_size(p, B, QSV_OP_FORWARD_EXPVAL));
     case QSV_OP_FORWARD_EXPVAL: {
@@ -2432,28 +2273,12 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
                 bytes += 16.0 * (double)B * (double)(int64_t(1) << c.W);
             }
         ev = prof_begin(p, s);
-        if (multi_persistent()) {
-            int* sync = (int*)((char*)ws + mats_bytes(p, B));
-            const int nsync = (int)(multi_sync_bytes(p) / sizeof(int));
-            unsigned grid = 1;
-            long long ticks = 0;
-            if ((rc = multi_launch_shape((const void*)k_multi_fwd_all, multi_lds(p), Q->n_fwd, &grid, &ticks)))
-                return rc;
-            hipLaunchKernelGGL(k_multi_sync_clear, dim3(1), dim3(256), 0, s, sync, nsync);
-            hipLaunchKernelGGL(k_multi_fwd_all, dim3(grid), dim3(256), multi_lds(p), s, (const DCirc*)T->circ,
-                               (const DItem*)Q->fwd, Q->n_fwd, (const DPass*)T->fwd_pass, (const DStage*)T->stages,
-                               (const DOp*)T->ops, (const DTerm*)T->terms, (const float*)mats, p->n_shared_mats,
-                               p->n_ps_mats, st, p->row, (int)B, sync, ticks);
-            hipLaunchKernelGGL(k_multi_poison, dim3(1), dim3(256), 0, s, (const int*)sync, st, p->row,
-                               (const DCirc*)T->circ, (int)p->circ.size(), (int)B);
-        } else {
-            for (size_t r = 0; r + 1 < Q->fwd_rounds.size(); ++r) {
-                const int i0 = Q->fwd_rounds[r], n = Q->fwd_rounds[r + 1] - i0;
-                hipLaunchKernelGGL(k_multi_fwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
-                                   (const DCirc*)T->circ, (const DItem*)(Q->fwd + i0), (const DPass*)T->fwd_pass,
-                                   (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
-                                   (const float*)mats, p->n_shared_mats, p->n_ps_mats, st, p->row);
-            }
+        for (size_t r = 0; r + 1 < Q->fwd_rounds.size(); ++r) {
+            const int i0 = Q->fwd_rounds[r], n = Q->fwd_rounds[r + 1] - i0;
+            hipLaunchKernelGGL(k_multi_fwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
+                               (const DCirc*)T->circ, (const DItem*)(Q->fwd + i0), (const DPass*)T->fwd_pass,
+                               (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
+                               (const float*)mats, p->n_shared_mats, p->n_ps_mats, st, p->row);
         }
         prof_end(p, s, ev, K_MULTI_FWD, bytes, flops);
         HIP_TRY(hipGetLastError());
@@ -2697,7 +2522,6 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     c += align256(state_bytes(p, B));
     double* part = (double*)c;
     c += partial_bytes(p, B);
-    int* sync = nullptr;  // persistent multi-circuit launches: their sync area, at c
     if ((rc = run_coef(p, T, w, x, B, mats, s))) return rc;
     const int64_t nch = grad_nch(p);
     const double amps = (double)B * (double)(int64_t(1) << W);
@@ -2713,29 +2537,14 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
                 bytes += (((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0)) * a;
             }
         hipEvent_t ev = prof_begin(p, s);
-        if (multi_persistent()) {
-            sync = (int*)c;
-            const int nsync = (int)(multi_sync_bytes(p) / sizeof(int));
-            unsigned grid = 1;
-            long long ticks = 0;
-            if ((rc = multi_launch_shape((const void*)k_multi_bwd_all, multi_lds(p), Q->n_bwd, &grid, &ticks)))
-                return rc;
-            hipLaunchKernelGGL(k_multi_sync_clear, dim3(1), dim3(256), 0, s, sync, nsync);
-            hipLaunchKernelGGL(k_multi_bwd_all, dim3(grid), dim3(256), multi_lds(p), s, (const DCirc*)T->circ,
-                               (const DItem*)Q->bwd, Q->n_bwd, (const DPass*)T->bwd_pass, (const DStage*)T->stages,
-                               (const DOp*)T->ops, (const DTerm*)T->terms, (const DGOut*)T->gouts,
-                               (const float*)mats, p->n_shared_mats, p->n_ps_mats, (const float2*)d_state, psi, lam,
-                               gout, p->Wtot, p->row, (int)B, part, (const int64_t*)T->pu, sync, ticks);
-        } else {
-            for (size_t r = 0; r + 1 < Q->bwd_rounds.size(); ++r) {
-                const int i0 = Q->bwd_rounds[r], n = Q->bwd_rounds[r + 1] - i0;
-                hipLaunchKernelGGL(k_multi_bwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
-                                   (const DCirc*)T->circ, (const DItem*)(Q->bwd + i0), (const DPass*)T->bwd_pass,
-                                   (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
-                                   (const DGOut*)T->gouts, (const float*)mats, p->n_shared_mats,
-                                   p->n_ps_mats, (const float2*)d_state, psi, lam, gout, p->Wtot, p->row, (int)B,
-                                   part, (const int64_t*)T->pu);
-            }
+        for (size_t r = 0; r + 1 < Q->bwd_rounds.size(); ++r) {
+            const int i0 = Q->bwd_rounds[r], n = Q->bwd_rounds[r + 1] - i0;
+            hipLaunchKernelGGL(k_multi_bwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
+                               (const DCirc*)T->circ, (const DItem*)(Q->bwd + i0), (const DPass*)T->bwd_pass,
+                               (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
+                               (const DGOut*)T->gouts, (const float*)mats, p->n_shared_mats,
+                               p->n_ps_mats, (const float2*)d_state, psi, lam, gout, p->Wtot, p->row, (int)B,
+                               part, (const int64_t*)T->pu);
         }
         prof_end(p, s, ev, K_MULTI_BWD, bytes, flops);
     } else if (p->opts.method == QSV_METHOD_PER_GATE) {
@@ -2802,7 +2611,7 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)n_out), dim3(256), 0, s,
                            (const double*)part, T->grad_csr, p->n_weights, p->n_inputs, (int)B,
                            (const int64_t*)T->pu, (const int32_t*)T->nchv, gw, gx, w,
-                           (int)p->opts.weight_remap, sync ? (const int*)(sync + 1) : (const int*)nullptr);
+                           (int)p->opts.weight_remap);
         prof_end(p, s, ev, K_GRAD_REDUCE, 8.0 * (double)std::max<int64_t>(p->pu_total, 1) * B, 0.0);
     }
     HIP_TRY(hipGetLastError());

@@ -1,11 +1,10 @@
-"""Many circuits in one plan (uneven batch: every pass of every circuit in one
-persistent launch per direction, or one launch per round of passes).
+"""Many circuits in one plan (uneven batch: pass r of every circuit in one
+launch per round of passes).
 
 Each circuit's slice of the combined state, expectations and gradients must
-equal the oracle run on that circuit alone; both launch forms must agree bit
-for bit; and the work list's order must let a persistent launch of any size
-drain without deadlock (checked by simulating the claim-and-wait protocol on
-the host).
+equal the oracle run on that circuit alone, and the work list's order must
+let a persistent launch of any size drain without deadlock (checked by
+simulating the claim-and-wait protocol on the host).
 """
 import heapq
 import os
@@ -234,6 +233,9 @@ def test_multi_uneven_512_sampled(orc):
 
 
 @pytest.mark.gpu
+@pytest.mark.skip(reason="the persistent multi-circuit launch (one launch per direction, items waiting on "
+                         "per-circuit counters) stopped making progress on its first device run and is "
+                         "switched off; the plan runs one launch per round")
 def test_multi_persistent_matches_rounds():
     """One persistent launch per direction and one launch per round run the
     same tile arithmetic: states, expectations and gradients bit for bit."""
