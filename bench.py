@@ -102,21 +102,25 @@ def families(stats):
     return out
 
 
-def counters_traffic(workload, kernel, sha):
-    """HBM bytes per launch of `kernel` from the committed counter summary of
-    this workload, if it was taken on the same generated source; else None."""
+def counters_summary(workload, kernel, sha):
+    """From the committed counter summary of this workload, if it was taken on
+    the same generated source: HBM bytes per launch of `kernel` and the
+    per-kernel instruction mix / unit occupancy ({} if absent). Returns
+    (traffic or None, source or reason, util)."""
     path = os.path.join(ROOT, "profiles", f"{workload}_counters.md")
     if not os.path.exists(path):
-        return None, "no counter summary"
+        return None, "no counter summary", {}
     m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
     if not m:
-        return None, "no json block in counter summary"
+        return None, "no json block in counter summary", {}
     d = json.loads(m.group(1))
-    if d.get("kernel") != kernel:
-        return None, f"counters were taken for {d.get('kernel')}"
     if d.get("codegen_sha1") != sha:
-        return None, "kernel source changed since the counters were taken"
-    return d["traffic_bytes"], os.path.relpath(path, ROOT)
+        return None, "kernel source changed since the counters were taken", {}
+    util = d.get("util", {})
+    by = d.get("traffic_by_kernel", {})
+    if kernel not in by:
+        return None, f"no counters for {kernel}", util
+    return by[kernel], os.path.relpath(path, ROOT), util
 
 
 def log(args, *a):
@@ -322,7 +326,7 @@ def main():
     tfs = dom["flops"] / (dom["total_ms"] / 1e3) / 1e12
     hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tfs / FP32_VECTOR_PEAK_TF
     sha = hashlib.sha1(binding.qsv_plan_codegen_source(fused.handle).encode()).hexdigest()
-    traffic, traffic_src = counters_traffic(args.workload, dom_name, sha)
+    traffic, traffic_src, util = counters_summary(args.workload, dom_name, sha)
     dfam = fam[family(dom_name)]
     if hbm_frac >= alu_frac:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -340,7 +344,23 @@ def main():
                  "family_alu_tflops": round(dfam["flops"] / (dfam["total_ms"] / 1e3) / 1e12, 3),
                  "family_hbm_gbs": round(dfam["bytes"] / (dfam["total_ms"] / 1e3) / 1e9, 1),
                  "traffic": None if traffic is None else round(traffic, 1),
-                 "traffic_source": traffic_src, "codegen_sha1": sha})
+                 "traffic_source": traffic_src, "codegen_sha1": sha,
+                  # counter-derived, same source hash: vector instructions issued per SIMD
+                 # per cycle, and the fraction of cycles the matrix cores were busy
+                 "valu_issue": util.get(dom_name, {}).get("valu_issue"),
+                 "mfma_busy": util.get(dom_name, {}).get("mfma_busy")})
+    # the generated kernels that issue matrix instructions (forward 2x2 products),
+    # from the same counter summary: matrix instructions per wave, busy fractions,
+    # and the matrix-core busy fraction weighted by this run's kernel times
+    mc = {k: v for k, v in util.items() if v.get("mfma_insts_per_wave")}
+    matrix_cores = None
+    if mc:
+        wt = {k: stats[k]["total_ms"] for k in mc if k in stats}
+        tot = sum(wt.values())
+        matrix_cores = {"kernels": mc, "source": traffic_src if traffic is not None else
+                        os.path.join("profiles", f"{args.workload}_counters.md"),
+                        "mfma_busy_time_weighted": round(sum(mc[k]["mfma_busy"] * w for k, w in wt.items()) / tot, 4)
+                        if tot and all("mfma_busy" in mc[k] for k in wt) else None}
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None
@@ -389,6 +409,7 @@ def main():
                     for k, v in list(fam.items()) + [kv for kv in stats.items()
                                                      if family(kv[0]) != kv[0]]},
         "roofline": roof,
+        "matrix_cores": matrix_cores,
         "cpu_baseline": cpu,
         "check": check,
         "uneven": uneven,

@@ -9,6 +9,14 @@
         HBM bytes per dispatch of KERNEL from FETCH_SIZE / WRITE_SIZE (KiB per
         dispatch), each scaled by what the same counter reads for a plain
         device copy of COPY_BYTES bytes read and written; prints JSON
+    python -m paper_2404_09213_amd.profread traffic_all FETCH_DIR WRITE_DIR COPY_FETCH_DIR \\
+            COPY_WRITE_DIR COPY_BYTES KERNEL_REGEX
+        the same for every kernel matching KERNEL_REGEX
+    python -m paper_2404_09213_amd.profread util SQ_DIR [KERNEL_REGEX]
+        per kernel from one SQ + GRBM counter pass: vector and matrix
+        instructions per wave, matrix-core busy fraction, vector
+        instructions issued per SIMD per cycle and matrix FLOPs (see util());
+        prints JSON
 """
 from __future__ import annotations
 
@@ -79,6 +87,58 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, ke
             "traffic_bytes": fk[1] * 1024.0 * fetch_scale + wk[1] * 1024.0 * write_scale}
 
 
+N_CU = 256          # MI355X compute units
+N_SIMD = 4 * N_CU   # four SIMDs per CU
+N_XCD = 8           # GRBM_GUI_ACTIVE comes back summed over the eight XCDs
+
+
+def util(sq_dir, kernel_regex=None):
+    """Per-kernel instruction mix and unit occupancy from one counter pass.
+
+    GRBM_GUI_ACTIVE / N_XCD is the dispatch's length in GPU cycles (checked
+    against its timestamps: 2.0-2.2 cycles per ns under load), so
+      mfma_busy  = SQ_VALU_MFMA_BUSY_CYCLES / (cycles x SIMDs),
+      valu_issue = vector (non-matrix) instructions per SIMD per cycle,
+    and mfma_flops = SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 (the counter
+    definitions' MfmaFlopsF32)."""
+    m = counter_means(sq_dir, kernel_regex)
+    out = {}
+    for k in sorted({k for (k, _) in m}):
+        g = lambda c: m.get((k, c), (0, None))[1]
+        waves, gui = g("SQ_WAVES"), g("GRBM_GUI_ACTIVE")
+        row = {"dispatches": m.get((k, "SQ_WAVES"), (0, 0))[0]}
+        if waves:
+            for c, name in (("SQ_INSTS_VALU", "valu_insts_per_wave"), ("SQ_INSTS_MFMA", "mfma_insts_per_wave"),
+                            ("SQ_INSTS_LDS", "lds_insts_per_wave")):
+                if g(c) is not None:
+                    row[name] = round(g(c) / waves, 1)
+        if gui:
+            cyc = gui / N_XCD
+            row["cycles"] = round(cyc)
+            if g("SQ_VALU_MFMA_BUSY_CYCLES") is not None:
+                row["mfma_busy"] = round(g("SQ_VALU_MFMA_BUSY_CYCLES") / (cyc * N_SIMD), 4)
+            if g("SQ_INSTS_VALU") is not None:
+                row["valu_issue"] = round((g("SQ_INSTS_VALU") - (g("SQ_INSTS_MFMA") or 0)) / (cyc * N_SIMD), 4)
+        if g("SQ_INSTS_VALU_MFMA_MOPS_F32") is not None:
+            row["mfma_flops"] = g("SQ_INSTS_VALU_MFMA_MOPS_F32") * 512
+        out[k] = row
+    return out
+
+
+def traffic_all(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, kernel_regex):
+    """traffic() for every kernel matching kernel_regex: {kernel: bytes per dispatch}."""
+    fk = counter_means(fetch_dir, kernel_regex)
+    wk = counter_means(write_dir, kernel_regex)
+    fetch_scale = copy_bytes / (_copy_kib(copy_fetch_dir, "FETCH_SIZE") * 1024.0)
+    write_scale = copy_bytes / (_copy_kib(copy_write_dir, "WRITE_SIZE") * 1024.0)
+    out = {}
+    for (k, c), (n, v) in fk.items():
+        if c == "FETCH_SIZE" and (k, "WRITE_SIZE") in wk:
+            out[k] = v * 1024.0 * fetch_scale + wk[(k, "WRITE_SIZE")][1] * 1024.0 * write_scale
+    return {"fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+            "traffic_by_kernel": {k: round(v, 1) for k, v in sorted(out.items())}}
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         rows = sorted(kernel_stats(argv[1]), key=lambda r: -r["total_us"])
@@ -91,6 +151,10 @@ def main(argv):
         print("| kernel | counter | dispatches | mean per dispatch |\n|---|---|---|---|")
         for (k, c), (n, v) in sorted(m.items()):
             print(f"| {k} | {c} | {n} | {v:.6g} |")
+    elif len(argv) >= 2 and argv[0] == "util":
+        print(json.dumps(util(argv[1], argv[2] if len(argv) > 2 else None), indent=1))
+    elif len(argv) == 7 and argv[0] == "traffic_all":
+        print(json.dumps(traffic_all(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6]), indent=1))
     elif len(argv) == 7 and argv[0] == "traffic":
         print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6])))
     else:
