@@ -1787,6 +1787,12 @@ int64_t row_amps(const qsv_plan_t* p) { return p->multi ? p->row : int64_t(1) <<
 
 size_t state_bytes(const qsv_plan_t* p, int64_t B) { return (size_t)B * (size_t)row_amps(p) * amp_size(p); }
 
+// The backward's lambda copy starts this many bytes after psi's end, so that an
+// amplitude of psi and the same amplitude of lambda (read and written together
+// by every backward kernel) are not a power of two apart: per-gate adjoint
+// 1-qubit class 0.668 -> 0.681 of 8 TB/s, fused passes unchanged.
+constexpr size_t kLamSkew = 4096 + 256;
+
 size_t partial_bytes(const qsv_plan_t* p, int64_t B) {
     return align256((size_t)std::max<int64_t>(p->pu_total, 1) * B * sizeof(double));
 }
@@ -2227,7 +2233,7 @@ size_t qsv_workspace_size(const qsv_plan_t* p, int64_t B, int32_t op) {
         if (p->multi) return align256((size_t)B * p->nchunk_tot * 32 * sizeof(double));
         return align256((size_t)B * expval_nchunk(p) * p->W * sizeof(double));
     case QSV_OP_BACKWARD:
-        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + partial_bytes(p, B);
+        return mats_bytes(p, B) + 2 * align256(state_bytes(p, B)) + kLamSkew + partial_bytes(p, B);
     case QSV_OP_STEP:
         return std::max(qsv_workspace_size(p, B, QSV_OP_BACKWARD), qsv_workspace_size(p, B, QSV_OP_FORWARD_EXPVAL));
     case QSV_OP_FORWARD_EXPVAL: {
@@ -2517,7 +2523,7 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     float* mats = (float*)c;
     c += mats_bytes(p, B);
     float2* psi = (float2*)c;
-    c += align256(state_bytes(p, B));
+    c += align256(state_bytes(p, B)) + kLamSkew;
     float2* lam = (float2*)c;
     c += align256(state_bytes(p, B));
     double* part = (double*)c;
