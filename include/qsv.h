@@ -107,6 +107,17 @@ typedef struct {
     int32_t q2;    /* target of a 2-control gate; -1 otherwise */
 } qsv_gate;
 
+/*
+ * Plan options. The paper names one knob, the largest number of qubits of a
+ * sub-circuit (section "Circuit Splitting"): fuse_width. The others are this
+ * library's. Work-group size is not an option: a fused pass uses
+ * max(64, 2^(tile_qubits - 4)) threads, 16 amplitudes each. Matrix-core use
+ * is the `mfma` bit mask (there is no dense-block path: a 3-qubit block as one
+ * 16x16x4 product measured slower than the 2x2 products it replaces).
+ * Choosing options by measurement is the Python tuner's job (tune.py, over
+ * qsv_plan_estimate and timed runs), and HIP-graph capture is a call of its
+ * own (qsv_graph_create), not an option.
+ */
 typedef struct {
     int32_t method;      /* QSV_METHOD_FUSED or QSV_METHOD_PER_GATE */
     int32_t fuse_width;  /* k: max qubits of a splitter block (section "Circuit
