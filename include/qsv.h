@@ -217,11 +217,11 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
  * executed in parallel); the call is this library's addition for batches of
  * unrelated circuits. Every circuit is split and scheduled as by qsv_plan
  * (fused method, table-driven kernels, tile_qubits <= 12). qsv_forward and
- * qsv_backward then run pass r of EVERY circuit in one launch ("round r"),
- * one workgroup per (circuit, tile) in the order of qsv_plan_multi_items; a
- * circuit's next pass is in the next round, so the number of launches per
- * direction is the largest pass count of any circuit, not the number of
- * circuits. No workgroup waits on another. (A single persistent launch per
+ * qsv_backward then run the passes of ALL circuits in a few launches
+ * ("rounds"), one workgroup per (circuit, tile), in the order of
+ * qsv_plan_multi_items: a circuit's passes sit in consecutive rounds, so
+ * the number of launches per direction is the largest pass count of any
+ * circuit, not the number of circuits. No workgroup waits on another. (A single persistent launch per
  * direction that walks the same list, each item waiting for its circuit's
  * previous pass, stopped making progress on its first device run; it is not
  * used.)
@@ -250,13 +250,14 @@ int64_t qsv_state_offset(const qsv_plan_t* plan, int32_t circuit);
 
 /*
  * Work list of a multi-circuit plan at this batch size, in the order one
- * forward (which = 0) or backward (which = 1) launch processes it: item i is
- * (circuit, pass, tile) at items[3i .. 3i+2]. Pass r of every circuit comes
- * after all tiles of its pass r - 1 (the list goes round by round, larger
- * circuits first within a round); a persistent launch taking items in this
- * order would start an item of pass r once every tile of pass r - 1 of its
- * circuit is done; the round launches run round r as one launch. Copies at
- * most max_items items (items may be NULL) and stores the total count in
+ * forward (which = 0) or backward (which = 1) runs it: item i is
+ * (circuit, pass, tile) at items[3i .. 3i+2]. The list goes round by round
+ * (one launch each); a circuit with k passes takes k consecutive rounds,
+ * starting where the rounds stay best balanced, so pass r of a circuit comes
+ * after all tiles of its pass r - 1; the costliest tiles of a round come
+ * first. (A persistent launch taking items in this order could start an item
+ * once every tile of its circuit's previous pass is done.) Copies at most
+ * max_items items (items may be NULL) and stores the total count in
  * *n_items. Host only.
  */
 int qsv_plan_multi_items(const qsv_plan_t* plan, int64_t batch, int32_t which, int32_t* items,

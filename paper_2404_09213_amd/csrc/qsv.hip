@@ -1895,25 +1895,61 @@ int check_batch(const qsv_plan_t* p, int64_t B) {
 }
 
 // Work list of one direction (dir 0 forward, 1 backward) of a multi-circuit
-// plan at batch B: round r lists every tile of pass r of every circuit that
-// has one, larger circuits first; rounds[r] is round r's first item (and
-// rounds.back() the item count). Every item's predecessors (all tiles of the
-// circuit's previous pass) come earlier in the list: the rounds run it as
-// one launch per round, and a single persistent launch could walk it in
-// order without deadlock (qsv_plan_multi_items exposes it for that check).
+// plan at batch B, as rounds (one launch each): rounds[r] is round r's first
+// item (and rounds.back() the item count). A circuit with k passes runs them
+// in k consecutive rounds s, s+1, ..., s+k-1, so every item's predecessors
+// (all tiles of its circuit's previous pass) are in the round before: the
+// kernel boundary orders them and no workgroup waits on another. The start
+// round s is chosen to balance the rounds: circuits in decreasing order of
+// estimated work (tile amplitudes x (the pass's float32 operations per
+// amplitude + 16, a byte-traffic allowance)) take the start that keeps the
+// busiest of their rounds least loaded (earliest on ties), which fills the
+// sparse late rounds with circuits that have fewer passes than the deepest
+// one. Within a round the most expensive tiles come first.
 void multi_items(const qsv_plan_t* p, int64_t B, int dir, std::vector<DItem>& items, std::vector<int>& rounds) {
-    std::vector<int> order(p->circ.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->circ[a].W > p->circ[b].W; });
-    int maxp = 0;
-    for (const DCirc& c : p->circ) maxp = std::max(maxp, dir ? c.n_bwd : c.n_fwd);
-    for (int r = 0; r < maxp; ++r) {
+    const int nc = (int)p->circ.size();
+    auto npass = [&](const DCirc& c) { return dir ? c.n_bwd : c.n_fwd; };
+    auto tile_cost = [&](const DCirc& c, int r) {
+        const double fl = dir ? p->bwd_pass_flops[c.bwd0 + r] : p->fwd_pass_flops[c.fwd0 + r];
+        return (double)(int64_t(1) << c.m) * (fl + 16.0);
+    };
+    auto ntiles = [&](const DCirc& c) { return (int)(B << (c.W - c.m)); };
+    int R = 0;
+    for (const DCirc& c : p->circ) R = std::max(R, npass(c));
+    std::vector<double> total(nc, 0.0);
+    for (int ci = 0; ci < nc; ++ci)
+        for (int r = 0; r < npass(p->circ[ci]); ++r) total[ci] += ntiles(p->circ[ci]) * tile_cost(p->circ[ci], r);
+    std::vector<int> order(nc);
+    for (int i = 0; i < nc; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return total[a] > total[b]; });
+    std::vector<double> load(R, 0.0);
+    std::vector<int> start(nc, 0);
+    for (int ci : order) {
+        const DCirc& c = p->circ[ci];
+        const int k = npass(c);
+        int best = 0;
+        double best_max = 0.0;
+        for (int s0 = 0; s0 + k <= R; ++s0) {
+            double mx = 0.0;
+            for (int j = 0; j < k; ++j) mx = std::max(mx, load[s0 + j] + ntiles(c) * tile_cost(c, j));
+            if (s0 == 0 || mx < best_max) { best = s0; best_max = mx; }
+        }
+        start[ci] = best;
+        for (int j = 0; j < k; ++j) load[best + j] += ntiles(c) * tile_cost(c, j);
+    }
+    for (int r = 0; r < R; ++r) {
         rounds.push_back((int)items.size());
-        for (int ci : order) {
-            const DCirc& c = p->circ[ci];
-            if (r >= (dir ? c.n_bwd : c.n_fwd)) continue;
-            const int ntiles = (int)(B << (c.W - c.m));
-            for (int t = 0; t < ntiles; ++t) items.push_back({ci, r, t, {0, 0, 0}});
+        std::vector<std::pair<double, int>> in;  // (tile cost, circuit) of the circuits with a pass in round r
+        for (int ci = 0; ci < nc; ++ci) {
+            const int j = r - start[ci];
+            if (j >= 0 && j < npass(p->circ[ci])) in.emplace_back(tile_cost(p->circ[ci], j), ci);
+        }
+        std::stable_sort(in.begin(), in.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+            return a.first > b.first;
+        });
+        for (const auto& e : in) {
+            const DCirc& c = p->circ[e.second];
+            for (int t = 0; t < ntiles(c); ++t) items.push_back({e.second, r - start[e.second], t, {0, 0, 0}});
         }
     }
     rounds.push_back((int)items.size());
