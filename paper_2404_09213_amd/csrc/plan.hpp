@@ -234,7 +234,7 @@ struct qsv_plan_s {
     std::vector<int32_t> nchv;
     int64_t pu_total = 0;
 
-    // multi-circuit plans: circuits simulated together by persistent launches
+    // multi-circuit plans: circuits simulated together, one launch per round of passes
     bool multi = false;
     std::vector<qsv::DCirc> circ;
     int Wtot = 0;          // expectation columns (sum of qubits)

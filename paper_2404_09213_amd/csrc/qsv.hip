@@ -6,11 +6,16 @@
 //   k_init          product-state init from the leading 1-qubit gates (embedding)
 //   k_pg_apply      plain method: one strided sweep of the state per gate
 //   k_pg_adj        plain method, backward: gradient partial + uncompute psi, lambda
+//   k_pg_apply_vec / k_pg_adj_vec   the same with 16-byte streaming accesses (complex64)
 //   k_adj_init      plain method: lambda = (sum_i g_i Z_i) psi_N
 //   k_pass_fwd      fused pass: tile of 2^m amplitudes, register stages, LDS re-layout
 //   k_pass_bwd      fused pass, backward: same tiles for psi and lambda + gradients
 //   k_expval_part / k_expval_final   <Z_i> readout, two deterministic stages
 //   k_grad_reduce   gradient partials -> weight (batch-summed) and input gradients
+//   k_multi_fwd / k_multi_bwd, k_init_multi, k_expval_part_multi / k_expval_final_multi
+//                   many circuits in one plan: fused passes as one launch per round
+// The fused passes of single-circuit plans normally run as kernels generated
+// for the plan (jit.cpp); k_pass_fwd / k_pass_bwd interpret the same tables.
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
