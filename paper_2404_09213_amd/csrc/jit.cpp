@@ -176,6 +176,7 @@ __device__ __forceinline__ f2 qsv_flip(f2 a, unsigned s) {
 private:
     const qsv_plan_t* p_;
     const DPass* ps_ = nullptr;
+    const Layout* lay_ = nullptr;  // register layout of the ops being emitted
     std::ostringstream o_;
     bool bwd_ = false, guard_ = false, last_fwd_ = false;
     std::string name_;
@@ -303,12 +304,27 @@ private:
             if (c >= 0 && c < kCtlNonReg && !(k >> c & 1)) return false;
         return true;
     }
-    // run-time condition of the op's controls outside the registers ("" if none)
-    static std::string nonreg_cond(const DOp& op) {
+    // Whether a control outside the registers sits on an index bit fed by one
+    // of the six lane bits of the thread index (the condition then differs
+    // between the lanes of a wave). Other controls are uniform over a wave:
+    // their bit lies outside the tile or comes from the wave index.
+    bool lane_ctl(const DOp& op) const {
+        for (int x : {op.ctl, op.ctl2}) {
+            if (x < kCtlNonReg) continue;
+            for (size_t i = 0; i < lay_->nonreg.size() && i < 6; ++i)
+                if (lq(lay_->nonreg[i]) == (x & 0xFF)) return true;
+        }
+        return false;
+    }
+    // run-time condition of the op's controls outside the registers ("" if
+    // none); a wave-uniform one is read from the first lane, so the compiler
+    // branches on a scalar and skips the op for waves where it is false
+    std::string nonreg_cond(const DOp& op) const {
         std::string c;
         for (int x : {op.ctl, op.ctl2})
             if (x >= kCtlNonReg) c += std::string(c.empty() ? "" : " && ") + "((gT >> " + I(x & 0xFF) + ") & 1)";
-        return c;
+        if (c.empty() || lane_ctl(op)) return c;
+        return "__builtin_amdgcn_readfirstlane((int)(" + c + "))";
     }
     std::vector<int> pairs(const DOp& op) const {
         std::vector<int> v;
@@ -430,6 +446,20 @@ private:
             return;
         }
         const std::string nc = nonreg_cond(op);
+        if (op.kind == OP_SWAP && !nc.empty() && lane_ctl(op)) {
+            // A swap under a per-lane control as selects: written as a branch,
+            // the compiler keeps both orders of every pair live across the
+            // divergent region (64 more VGPRs for psi and lambda).
+            o_ << "    const bool c_ = " << nc << ";\n";
+            for (const std::string& A : arrays_)
+                for (int k : pairs(op)) {
+                    const std::string x = rk(A, k), y = rk(A, k | (1 << op.pos));
+                    o_ << "    { const f2 x = " << x << ", y = " << y << "; " << x << " = c_ ? y : x; " << y
+                       << " = c_ ? x : y; }\n";
+                }
+            o_ << "  }\n";
+            return;
+        }
         if (!nc.empty()) o_ << "    if (" << nc << ") {\n";
         if (use_mfma(op)) emit_pairs_mfma(op);
         for (const std::string& A : arrays_)
@@ -692,6 +722,7 @@ private:
                 emit_exchange(cur, L);
                 cur = L;
             }
+            lay_ = &cur;
             for (int oi = st.op0; oi < st.op1; ++oi) {
                 const DOp& op = p_->ops[oi];
                 if (op.kind >= OP_GX) {
