@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--pack-beam", type=int, default=None)
     ap.add_argument("--uneven-steps", type=int, default=15,
                     help="timed steps of the 512-circuit uneven set (0 = skip)")
+    ap.add_argument("--pass-copy", type=int, choices=(0, 1), default=1,
+                    help="time each generated pass's loads and stores alone (qsv_pass_copy)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: time a plain 1 GiB device copy (counter calibration)")
@@ -156,6 +158,49 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
     stats = plan.profile_read()
     plan.profile(False)
     return total_ms / steps, stats, step_ms
+
+
+# LDS reserved per workgroup by the copy measurement: 0, then 6, 5, 4, 3 and 2
+# tiles per compute unit (160 KB each)
+COPY_LDS = (0, 24576, 32768, 40960, 53248, 65536)
+
+
+def pass_copies(plan, info, B, W, stats, torch, reps=3):
+    """Every generated pass beside a plain copy of its own memory accesses: the
+    same loads and stores through the same tiles with no arithmetic
+    (qsv_pass_copy), at several residencies (LDS reserved per workgroup), timed
+    with events on the stream it runs on; the fastest residency is kept.
+    copy_over_pass near 1 means the pass takes as long as its accesses alone."""
+    dev = torch.device("cuda:0")
+    a = torch.zeros((B, 1 << W), dtype=torch.complex64, device=dev)
+    b = torch.zeros_like(a)
+    stream = torch.cuda.current_stream()
+    passes = {}
+    for which, count, prefix in ((0, info["n_fwd_passes"], "qsv_f"), (1, info["n_bwd_passes"], "qsv_b")):
+        for i in range(count):
+            name = f"{prefix}{i}"
+            if name not in stats:
+                return None  # not the generated kernels (table-driven passes)
+            by_lds = []
+            for lds in COPY_LDS:
+                plan.pass_copy(which, i, B, a, b, lds)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    plan.pass_copy(which, i, B, a, b, lds)
+                e1.record(stream)
+                e1.synchronize()
+                by_lds.append(round(e0.elapsed_time(e1) * 1e3 / reps, 1))
+            copy_us = min(by_lds)
+            pass_us = stats[name]["total_ms"] / stats[name]["launches"] * 1e3
+            passes[name] = {"pass_us": round(pass_us, 1), "copy_us": copy_us,
+                            "copy_lds": COPY_LDS[by_lds.index(copy_us)], "copy_us_by_lds": by_lds,
+                            "copy_over_pass": round(copy_us / pass_us, 4)}
+    del a, b
+    sum_copy = sum(v["copy_us"] for v in passes.values()) / 1e3
+    sum_pass = sum(v["pass_us"] for v in passes.values()) / 1e3
+    return {"lds_sweep": list(COPY_LDS), "passes": passes, "copy_ms_per_step": round(sum_copy, 3),
+            "pass_ms_per_step": round(sum_pass, 3), "copy_over_pass": round(sum_copy / sum_pass, 4)}
 
 
 def step_spread(ms_list):
@@ -319,6 +364,7 @@ def main():
         log(args, f"[bench] per-gate: {pms:.3f} ms/step  {pg}")
 
     uneven = bench_uneven(args, torch, dev, binding, inputs) if args.uneven_steps > 0 else None
+    copies = pass_copies(fused, info, B, W, stats, torch) if args.pass_copy else None
 
     # roofline of the dominant kernel (largest share of the timed region)
     dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
@@ -348,7 +394,13 @@ def main():
                   # counter-derived, same source hash: vector instructions issued per SIMD
                  # per cycle, and the fraction of cycles the matrix cores were busy
                  "valu_issue": util.get(dom_name, {}).get("valu_issue"),
-                 "mfma_busy": util.get(dom_name, {}).get("mfma_busy")})
+                 "mfma_busy": util.get(dom_name, {}).get("mfma_busy"),
+                 # the same pass's loads and stores alone in a plain copy kernel
+                 # (qsv_pass_copy), and that time over the pass's own
+                 "copy_ms": None if not copies or dom_name not in copies["passes"] else
+                 round(copies["passes"][dom_name]["copy_us"] / 1e3, 4),
+                 "copy_over_pass": None if not copies or dom_name not in copies["passes"] else
+                 copies["passes"][dom_name]["copy_over_pass"]})
     # the generated kernels that issue matrix instructions (forward 2x2 products),
     # from the same counter summary: matrix instructions per wave, busy fractions,
     # and the matrix-core busy fraction weighted by this run's kernel times
@@ -409,6 +461,7 @@ def main():
                     for k, v in list(fam.items()) + [kv for kv in stats.items()
                                                      if family(kv[0]) != kv[0]]},
         "roofline": roof,
+        "pass_copy": copies,
         "matrix_cores": matrix_cores,
         "cpu_baseline": cpu,
         "check": check,

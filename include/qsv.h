@@ -404,6 +404,29 @@ int qsv_plan_codegen_source(const qsv_plan_t* plan, char* buf, size_t buf_size, 
 int qsv_plan_codegen_check(const qsv_plan_t* plan, const char* arch);
 
 /*
+ * Memory accesses of one fused pass alone, a measurement aid (not part of
+ * the paper's method): the global loads and stores of pass `pass` of the
+ * forward (which = 0) or backward (which = 1) schedule in a plain copy
+ * kernel, with no arithmetic between them, through the same tiles, thread
+ * layout, 16-byte pairs and block order as the pass kernel generated for it.
+ * A pass that takes about as long is bound by its accesses (it can also be
+ * faster: the copy issues every tile's stores right behind its loads, the
+ * pass spreads them out). d_a stands for the state (forward) or psi (backward), d_b for
+ * lambda: batch x 2^n complex64 each, 16-byte aligned when the pass's tiles
+ * hold amplitude bit 0 (else 8-byte). A forward pass reads and writes d_a
+ * (the first, which builds the product state, only writes: zeros); a backward
+ * pass reads and writes d_a and d_b (the first reads d_a only and writes it
+ * to both, the last writes nothing). Values read are written back unchanged;
+ * d_b may be NULL where it is not used. lds_bytes (0 to 65536) of LDS are
+ * reserved per workgroup without being used, which bounds how many tiles a
+ * compute unit holds at once (160 KB each; the pass kernels themselves
+ * reserve 32-36 KB, 4-5 tiles). Fused complex64 plans of one circuit only
+ * (QSV_ERR_ARG otherwise). Launches on `stream`.
+ */
+int qsv_pass_copy(const qsv_plan_t* plan, int32_t which, int32_t pass, int64_t batch, void* d_a,
+                  void* d_b, int32_t lds_bytes, void* stream);
+
+/*
  * Kernel profiling. While enabled, every kernel launch made by qsv_forward,
  * qsv_forward_expval, qsv_expval and qsv_backward with this plan is bracketed
  * by two HIP events recorded on the call's stream, and the launch's

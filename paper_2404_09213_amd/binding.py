@@ -77,7 +77,7 @@ EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_o
            "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_forward_expval_noalloc",
            "qsv_backward", "qsv_plan_get_info",
            "qsv_plan_gate_order", "qsv_plan_gate_blocks", "qsv_plan_codegen_source",
-           "qsv_plan_codegen_check", "qsv_plan_estimate", "qsv_graph_create", "qsv_graph_launch",
+           "qsv_plan_codegen_check", "qsv_plan_estimate", "qsv_pass_copy", "qsv_graph_create", "qsv_graph_launch",
            "qsv_graph_destroy", "qsv_profile_enable",
            "qsv_profile_read", "qsv_strerror", "qsv_last_error")
 
@@ -143,6 +143,8 @@ def lib():
         L.qsv_plan_estimate.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_double)]
         L.qsv_plan_estimate.restype = ctypes.c_int
+        L.qsv_pass_copy.argtypes = [vp, i32, i32, i64, vp, vp, i32, vp]
+        L.qsv_pass_copy.restype = ctypes.c_int
         L.qsv_graph_create.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
                                        ctypes.POINTER(vp)]
         L.qsv_graph_create.restype = ctypes.c_int
@@ -281,6 +283,10 @@ def qsv_plan_estimate(h, batch, hbm_gbs, alu_tflops, launch_us):
     _check(lib().qsv_plan_estimate(h, int(batch), float(hbm_gbs), float(alu_tflops), float(launch_us),
                                    ctypes.byref(us)))
     return us.value
+
+
+def qsv_pass_copy(h, which, pass_index, batch, d_a, d_b, lds_bytes, stream):
+    _check(lib().qsv_pass_copy(h, which, pass_index, batch, d_a, d_b, lds_bytes, stream))
 
 
 def qsv_plan_gate_order(h, which, n_gates):
@@ -498,6 +504,11 @@ class Plan:
         qsv_forward_expval_noalloc(self.handle, self._ptr(_f32(weights)), self._ptr(_f32(inputs)), batch,
                                    self._ptr(state), self._ptr(out), self._stream(dev))
         return state, out
+
+    def pass_copy(self, which, pass_index, batch, a, b=None, lds_bytes=0):
+        """qsv_pass_copy on torch complex64 arrays a (state / psi) and b (lambda)."""
+        qsv_pass_copy(self.handle, which, pass_index, batch, self._ptr(a), self._ptr(b) if b is not None else None,
+                      lds_bytes, self._stream(a.device))
 
     def backward(self, weights, inputs, state, grad_out, want_inputs=True, gw=None, gx=None):
         import torch

@@ -1613,6 +1613,86 @@ __global__ __launch_bounds__(256) void k_expval_final_multi(const DCirc* __restr
 }
 
 // ----------------------------------------------------------------------------
+// memory accesses of a fused pass alone (measurement aid)
+// ----------------------------------------------------------------------------
+// The global loads and stores of one generated pass kernel with nothing in
+// between: the same tiles, 16 amplitudes per thread, register bits (tile bit 0
+// when it is amplitude bit 0, else the fourth-highest tile bit, plus the top
+// three), thread-index bits on the other tile bits in ascending order,
+// 16-byte pairs when tile bit 0 is amplitude bit 0, and the XCD-contiguous
+// block order. rd / wr: bit 0 array a, bit 1 array b.
+struct PassGeom {
+    int32_t m, W, tb, pair;
+    int32_t lq[kMaxQ];  // tile bit j -> amplitude bit
+    int32_t oq[kMaxQ];  // tile-index bit k -> amplitude bit
+};
+
+__global__ __launch_bounds__(256) void k_pass_copy(float2* __restrict__ a, float2* __restrict__ bb,
+                                                   const PassGeom g, int rd, int wr) {
+    const int t = threadIdx.x;
+    if (t >= (1 << (g.m - kRegBits))) return;  // no barriers below
+    const unsigned tile = (gridDim.x & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const unsigned s = tile >> g.tb, tis = tile & ((1u << g.tb) - 1u);
+    size_t base = (size_t)s << g.W;
+    for (int k = 0; k < g.tb; ++k) base |= (size_t)((tis >> k) & 1u) << g.oq[k];
+    const int r0 = g.pair ? 0 : g.m - 4;
+    size_t gT = base;
+    for (int j = 0, i = 0; j < g.m; ++j) {
+        if (j == r0 || j >= g.m - 3) continue;
+        gT |= (size_t)((t >> i) & 1) << g.lq[j];
+        ++i;
+    }
+    const int s0 = g.lq[r0], s1 = g.lq[g.m - 3], s2 = g.lq[g.m - 2], s3 = g.lq[g.m - 1];
+    float2 va[kRegs], vb[kRegs];
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k) va[k] = vb[k] = make_float2(0.f, 0.f);
+    // offset of register pair k, k + 1 (k even); array by array, like the passes
+    auto off = [&](int k) {
+        return gT + ((size_t)((k >> 1) & 1) << s1) + ((size_t)((k >> 2) & 1) << s2) + ((size_t)((k >> 3) & 1) << s3);
+    };
+    auto load = [&](const float2* __restrict__ x, float2 (&v)[kRegs]) {
+#pragma unroll
+        for (int k = 0; k < kRegs; k += 2) {
+            const size_t o = off(k);
+            if (g.pair) {
+                const float4 q = *reinterpret_cast<const float4*>(x + o);
+                v[k] = make_float2(q.x, q.y);
+                v[k + 1] = make_float2(q.z, q.w);
+            } else {
+                v[k] = x[o];
+                v[k + 1] = x[o + ((size_t)1 << s0)];
+            }
+        }
+    };
+    auto store = [&](float2* __restrict__ x, const float2 (&v)[kRegs]) {
+#pragma unroll
+        for (int k = 0; k < kRegs; k += 2) {
+            const size_t o = off(k);
+            if (g.pair) {
+                *reinterpret_cast<float4*>(x + o) = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+            } else {
+                x[o] = v[k];
+                x[o + ((size_t)1 << s0)] = v[k + 1];
+            }
+        }
+    };
+    if (rd & 1) load(a, va);
+    if (rd & 2) load(bb, vb);
+    else {
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) vb[k] = va[k];
+    }
+    if (!wr) {
+        // keep the loads: their values feed an empty asm statement
+#pragma unroll
+        for (int k = 0; k < kRegs; ++k) __asm__ volatile("" ::"v"(va[k].x), "v"(va[k].y), "v"(vb[k].x), "v"(vb[k].y));
+        return;
+    }
+    if (wr & 1) store(a, va);
+    if (wr & 2) store(bb, vb);
+}
+
+// ----------------------------------------------------------------------------
 // host side: device tables
 // ----------------------------------------------------------------------------
 namespace {
@@ -2932,6 +3012,52 @@ int qsv_plan_codegen_check(const qsv_plan_t* p, const char* arch) {
     rc = jit_compile(p, arch, jm, err);
     if (rc) set_error(err);
     return rc;
+}
+
+int qsv_pass_copy(const qsv_plan_t* p, int32_t which, int32_t pass, int64_t B, void* d_a, void* d_b,
+                  int32_t lds_bytes, void* stream) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (p->multi || p->opts.method != QSV_METHOD_FUSED || c128(p)) {
+        set_error("pass copy: fused complex64 plans of one circuit only");
+        return QSV_ERR_ARG;
+    }
+    if ((rc = check_batch(p, B))) return rc;
+    if (which != 0 && which != 1) { set_error("pass copy: which must be 0 or 1"); return QSV_ERR_ARG; }
+    const std::vector<DPass>& passes = which == 0 ? p->fwd_pass : p->bwd_pass;
+    if (pass < 0 || pass >= (int32_t)passes.size()) { set_error("pass copy: no such pass"); return QSV_ERR_ARG; }
+    const DPass& ps = passes[pass];
+    int rd, wr;
+    if (which == 0) {
+        rd = (ps.flags & PF_INIT_FWD) ? 0 : 1;
+        wr = 1;
+    } else {
+        rd = (ps.flags & PF_FIRST_BWD) ? 1 : 3;
+        wr = (ps.flags & PF_LAST_BWD) ? 0 : 3;
+    }
+    if (!d_a || (((rd | wr) & 2) && !d_b)) { set_error("pass copy: null array"); return QSV_ERR_ARG; }
+    const int m = ps.m;
+    const bool pair = ps.lq[0] == 0;
+    const uintptr_t al = pair ? 15 : 7;
+    if (((uintptr_t)d_a & al) || (d_b && ((uintptr_t)d_b & al))) {
+        set_error("pass copy: arrays must be 16-byte aligned");
+        return QSV_ERR_ARG;
+    }
+    if (m < kRegBits + 1 || m > p->W) { set_error("pass copy: tile too small"); return QSV_ERR_ARG; }
+    if (lds_bytes < 0 || lds_bytes > 65536) { set_error("pass copy: lds_bytes outside 0..65536"); return QSV_ERR_ARG; }
+    PassGeom g{};
+    g.m = m;
+    g.W = p->W;
+    g.tb = p->W - m;
+    g.pair = pair ? 1 : 0;
+    for (int j = 0; j < m; ++j) g.lq[j] = ps.lq[j];
+    for (int k = 0; k < g.tb; ++k) g.oq[k] = ps.oq[k];
+    const uint64_t tiles = (uint64_t)B << g.tb;
+    const int threads = std::max(64, 1 << (m - kRegBits));
+    hipLaunchKernelGGL(k_pass_copy, dim3((unsigned)tiles), dim3(threads), (size_t)lds_bytes, (hipStream_t)stream,
+                       (float2*)d_a, (float2*)d_b, g, rd, wr);
+    HIP_TRY(hipGetLastError());
+    return QSV_OK;
 }
 
 int qsv_profile_enable(qsv_plan_t* p, int32_t on) {
