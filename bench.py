@@ -165,15 +165,14 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
 COPY_LDS = (0, 24576, 32768, 40960, 53248, 65536)
 
 
-def pass_copies(plan, info, B, W, stats, torch, reps=3):
+def pass_copies(plan, info, B, state, stats, torch, reps=3):
     """Every generated pass beside a plain copy of its own memory accesses: the
-    same loads and stores through the same tiles with no arithmetic
+    same loads and stores on the same arrays (the state; psi and lambda in the
+    backward workspace) through the same tiles, with no arithmetic
     (qsv_pass_copy), at several residencies (LDS reserved per workgroup), timed
-    with events on the stream it runs on; the fastest residency is kept.
-    copy_over_pass near 1 means the pass takes as long as its accesses alone."""
-    dev = torch.device("cuda:0")
-    a = torch.zeros((B, 1 << W), dtype=torch.complex64, device=dev)
-    b = torch.zeros_like(a)
+    with events on the stream the passes run on; the fastest residency is kept.
+    copy_over_pass near 1 means the pass takes as long as its accesses alone.
+    Runs after the timed steps: it overwrites the state and the workspace."""
     stream = torch.cuda.current_stream()
     passes = {}
     for which, count, prefix in ((0, info["n_fwd_passes"], "qsv_f"), (1, info["n_bwd_passes"], "qsv_b")):
@@ -183,11 +182,11 @@ def pass_copies(plan, info, B, W, stats, torch, reps=3):
                 return None  # not the generated kernels (table-driven passes)
             by_lds = []
             for lds in COPY_LDS:
-                plan.pass_copy(which, i, B, a, b, lds)
+                plan.pass_copy(which, i, B, state, lds)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 for _ in range(reps):
-                    plan.pass_copy(which, i, B, a, b, lds)
+                    plan.pass_copy(which, i, B, state, lds)
                 e1.record(stream)
                 e1.synchronize()
                 by_lds.append(round(e0.elapsed_time(e1) * 1e3 / reps, 1))
@@ -196,7 +195,6 @@ def pass_copies(plan, info, B, W, stats, torch, reps=3):
             passes[name] = {"pass_us": round(pass_us, 1), "copy_us": copy_us,
                             "copy_lds": COPY_LDS[by_lds.index(copy_us)], "copy_us_by_lds": by_lds,
                             "copy_over_pass": round(copy_us / pass_us, 4)}
-    del a, b
     sum_copy = sum(v["copy_us"] for v in passes.values()) / 1e3
     sum_pass = sum(v["pass_us"] for v in passes.values()) / 1e3
     return {"lds_sweep": list(COPY_LDS), "passes": passes, "copy_ms_per_step": round(sum_copy, 3),
@@ -364,7 +362,7 @@ def main():
         log(args, f"[bench] per-gate: {pms:.3f} ms/step  {pg}")
 
     uneven = bench_uneven(args, torch, dev, binding, inputs) if args.uneven_steps > 0 else None
-    copies = pass_copies(fused, info, B, W, stats, torch) if args.pass_copy else None
+    copies = pass_copies(fused, info, B, state, stats, torch) if args.pass_copy else None
 
     # roofline of the dominant kernel (largest share of the timed region)
     dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["total_ms"])

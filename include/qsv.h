@@ -407,24 +407,28 @@ int qsv_plan_codegen_check(const qsv_plan_t* plan, const char* arch);
  * Memory accesses of one fused pass alone, a measurement aid (not part of
  * the paper's method): the global loads and stores of pass `pass` of the
  * forward (which = 0) or backward (which = 1) schedule in a plain copy
- * kernel, with no arithmetic between them, through the same tiles, thread
- * layout, 16-byte pairs and block order as the pass kernel generated for it.
- * A pass that takes about as long is bound by its accesses (it can also be
- * faster: the copy issues every tile's stores right behind its loads, the
- * pass spreads them out). d_a stands for the state (forward) or psi (backward), d_b for
- * lambda: batch x 2^n complex64 each, 16-byte aligned when the pass's tiles
- * hold amplitude bit 0 (else 8-byte). A forward pass reads and writes d_a
- * (the first, which builds the product state, only writes: zeros); a backward
- * pass reads and writes d_a and d_b (the first reads d_a only and writes it
- * to both, the last writes nothing). Values read are written back unchanged;
- * d_b may be NULL where it is not used. lds_bytes (0 to 65536) of LDS are
- * reserved per workgroup without being used, which bounds how many tiles a
- * compute unit holds at once (160 KB each; the pass kernels themselves
- * reserve 32-36 KB, 4-5 tiles). Fused complex64 plans of one circuit only
- * (QSV_ERR_ARG otherwise). Launches on `stream`.
+ * kernel, with no arithmetic between them, on the arrays the pass itself
+ * uses and through the same tiles, thread layout, 16-byte pairs and block
+ * order as the pass kernel generated for it. A pass that takes about as long
+ * is bound by its accesses (it can also be faster: the copy issues every
+ * tile's stores right behind its loads, the pass spreads them out).
+ *   which = 0: reads and writes d_state (batch x 2^n complex64) in place,
+ *     values unchanged; the first pass, which builds the product state,
+ *     only writes it: zeros. d_ws may be NULL.
+ *   which = 1: d_ws of at least qsv_workspace_size(plan, batch,
+ *     QSV_OP_BACKWARD) bytes, whose psi and lambda copies (where
+ *     qsv_backward keeps them) are read and written; the first pass reads
+ *     d_state instead and writes its values to both, the last writes
+ *     nothing. d_state is not written.
+ * lds_bytes (0 to 65536) of LDS are reserved per workgroup without being
+ * used, which bounds how many tiles a compute unit holds at once (160 KB
+ * each; the pass kernels themselves reserve 32-36 KB, 4-5 tiles). Arrays are
+ * 16-byte aligned when the pass's tiles hold amplitude bit 0 (else 8-byte).
+ * Fused complex64 plans of one circuit only (QSV_ERR_ARG otherwise).
+ * Launches on `stream`.
  */
-int qsv_pass_copy(const qsv_plan_t* plan, int32_t which, int32_t pass, int64_t batch, void* d_a,
-                  void* d_b, int32_t lds_bytes, void* stream);
+int qsv_pass_copy(const qsv_plan_t* plan, int32_t which, int32_t pass, int64_t batch, void* d_state,
+                  void* d_ws, size_t ws_bytes, int32_t lds_bytes, void* stream);
 
 /*
  * Kernel profiling. While enabled, every kernel launch made by qsv_forward,

@@ -143,7 +143,7 @@ def lib():
         L.qsv_plan_estimate.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_double)]
         L.qsv_plan_estimate.restype = ctypes.c_int
-        L.qsv_pass_copy.argtypes = [vp, i32, i32, i64, vp, vp, i32, vp]
+        L.qsv_pass_copy.argtypes = [vp, i32, i32, i64, vp, vp, sz, i32, vp]
         L.qsv_pass_copy.restype = ctypes.c_int
         L.qsv_graph_create.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
                                        ctypes.POINTER(vp)]
@@ -285,8 +285,8 @@ def qsv_plan_estimate(h, batch, hbm_gbs, alu_tflops, launch_us):
     return us.value
 
 
-def qsv_pass_copy(h, which, pass_index, batch, d_a, d_b, lds_bytes, stream):
-    _check(lib().qsv_pass_copy(h, which, pass_index, batch, d_a, d_b, lds_bytes, stream))
+def qsv_pass_copy(h, which, pass_index, batch, d_state, d_ws, ws_bytes, lds_bytes, stream):
+    _check(lib().qsv_pass_copy(h, which, pass_index, batch, d_state, d_ws, ws_bytes, lds_bytes, stream))
 
 
 def qsv_plan_gate_order(h, which, n_gates):
@@ -505,10 +505,12 @@ class Plan:
                                    self._ptr(state), self._ptr(out), self._stream(dev))
         return state, out
 
-    def pass_copy(self, which, pass_index, batch, a, b=None, lds_bytes=0):
-        """qsv_pass_copy on torch complex64 arrays a (state / psi) and b (lambda)."""
-        qsv_pass_copy(self.handle, which, pass_index, batch, self._ptr(a), self._ptr(b) if b is not None else None,
-                      lds_bytes, self._stream(a.device))
+    def pass_copy(self, which, pass_index, batch, state, lds_bytes=0):
+        """qsv_pass_copy on a torch complex64 state; a backward pass runs on the
+        backward workspace this plan uses for the current stream."""
+        ws = self.workspace(batch, OP_BACKWARD, state.device) if which == 1 else None
+        qsv_pass_copy(self.handle, which, pass_index, batch, self._ptr(state), self._ptr(ws),
+                      0 if ws is None else ws.numel(), lds_bytes, self._stream(state.device))
 
     def backward(self, weights, inputs, state, grad_out, want_inputs=True, gw=None, gx=None):
         import torch

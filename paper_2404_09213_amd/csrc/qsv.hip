@@ -14,6 +14,7 @@
 //   k_grad_reduce   gradient partials -> weight (batch-summed) and input gradients
 //   k_multi_fwd / k_multi_bwd, k_init_multi, k_expval_part_multi / k_expval_final_multi
 //                   many circuits in one plan: fused passes as one launch per round
+//   k_pass_copy     measurement aid: a generated pass's loads and stores alone
 // The fused passes of single-circuit plans normally run as kernels generated
 // for the plan (jit.cpp); k_pass_fwd / k_pass_bwd interpret the same tables.
 #include <hip/hip_runtime.h>
@@ -1620,14 +1621,16 @@ __global__ __launch_bounds__(256) void k_expval_final_multi(const DCirc* __restr
 // when it is amplitude bit 0, else the fourth-highest tile bit, plus the top
 // three), thread-index bits on the other tile bits in ascending order,
 // 16-byte pairs when tile bit 0 is amplitude bit 0, and the XCD-contiguous
-// block order. rd / wr: bit 0 array a, bit 1 array b.
+// block order. rd / wr: bit 0 array a, bit 1 array b (read from ra / rb,
+// written to wa / wb; b takes a's values where b is not read). A thread reads
+// all its amplitudes before it writes any, so ra may be wa and rb may be wb.
 struct PassGeom {
     int32_t m, W, tb, pair;
     int32_t lq[kMaxQ];  // tile bit j -> amplitude bit
     int32_t oq[kMaxQ];  // tile-index bit k -> amplitude bit
 };
 
-__global__ __launch_bounds__(256) void k_pass_copy(float2* __restrict__ a, float2* __restrict__ bb,
+__global__ __launch_bounds__(256) void k_pass_copy(const float2* ra, const float2* rb, float2* wa, float2* wb,
                                                    const PassGeom g, int rd, int wr) {
     const int t = threadIdx.x;
     if (t >= (1 << (g.m - kRegBits))) return;  // no barriers below
@@ -1650,7 +1653,7 @@ __global__ __launch_bounds__(256) void k_pass_copy(float2* __restrict__ a, float
     auto off = [&](int k) {
         return gT + ((size_t)((k >> 1) & 1) << s1) + ((size_t)((k >> 2) & 1) << s2) + ((size_t)((k >> 3) & 1) << s3);
     };
-    auto load = [&](const float2* __restrict__ x, float2 (&v)[kRegs]) {
+    auto load = [&](const float2* x, float2 (&v)[kRegs]) {
 #pragma unroll
         for (int k = 0; k < kRegs; k += 2) {
             const size_t o = off(k);
@@ -1664,7 +1667,7 @@ __global__ __launch_bounds__(256) void k_pass_copy(float2* __restrict__ a, float
             }
         }
     };
-    auto store = [&](float2* __restrict__ x, const float2 (&v)[kRegs]) {
+    auto store = [&](float2* x, const float2 (&v)[kRegs]) {
 #pragma unroll
         for (int k = 0; k < kRegs; k += 2) {
             const size_t o = off(k);
@@ -1676,8 +1679,8 @@ __global__ __launch_bounds__(256) void k_pass_copy(float2* __restrict__ a, float
             }
         }
     };
-    if (rd & 1) load(a, va);
-    if (rd & 2) load(bb, vb);
+    if (rd & 1) load(ra, va);
+    if (rd & 2) load(rb, vb);
     else {
 #pragma unroll
         for (int k = 0; k < kRegs; ++k) vb[k] = va[k];
@@ -1688,8 +1691,8 @@ __global__ __launch_bounds__(256) void k_pass_copy(float2* __restrict__ a, float
         for (int k = 0; k < kRegs; ++k) __asm__ volatile("" ::"v"(va[k].x), "v"(va[k].y), "v"(vb[k].x), "v"(vb[k].y));
         return;
     }
-    if (wr & 1) store(a, va);
-    if (wr & 2) store(bb, vb);
+    if (wr & 1) store(wa, va);
+    if (wr & 2) store(wb, vb);
 }
 
 // ----------------------------------------------------------------------------
@@ -3014,8 +3017,8 @@ int qsv_plan_codegen_check(const qsv_plan_t* p, const char* arch) {
     return rc;
 }
 
-int qsv_pass_copy(const qsv_plan_t* p, int32_t which, int32_t pass, int64_t B, void* d_a, void* d_b,
-                  int32_t lds_bytes, void* stream) {
+int qsv_pass_copy(const qsv_plan_t* p, int32_t which, int32_t pass, int64_t B, void* d_state, void* ws,
+                  size_t ws_bytes, int32_t lds_bytes, void* stream) {
     int rc = check_plan(p);
     if (rc) return rc;
     if (p->multi || p->opts.method != QSV_METHOD_FUSED || c128(p)) {
@@ -3026,25 +3029,41 @@ int qsv_pass_copy(const qsv_plan_t* p, int32_t which, int32_t pass, int64_t B, v
     if (which != 0 && which != 1) { set_error("pass copy: which must be 0 or 1"); return QSV_ERR_ARG; }
     const std::vector<DPass>& passes = which == 0 ? p->fwd_pass : p->bwd_pass;
     if (pass < 0 || pass >= (int32_t)passes.size()) { set_error("pass copy: no such pass"); return QSV_ERR_ARG; }
+    if (lds_bytes < 0 || lds_bytes > 65536) { set_error("pass copy: lds_bytes outside 0..65536"); return QSV_ERR_ARG; }
     const DPass& ps = passes[pass];
+    const int m = ps.m;
+    if (m < kRegBits + 1 || m > p->W) { set_error("pass copy: tile too small"); return QSV_ERR_ARG; }
+    if (!d_state) { set_error("pass copy: null state"); return QSV_ERR_ARG; }
+    // the arrays the pass itself reads and writes: the state (forward, and
+    // psi_N for the first backward pass), psi and lambda in the backward workspace
+    float2 *ra = nullptr, *rb = nullptr, *wa = nullptr, *wb = nullptr;
     int rd, wr;
     if (which == 0) {
         rd = (ps.flags & PF_INIT_FWD) ? 0 : 1;
         wr = 1;
+        ra = wa = (float2*)d_state;
     } else {
-        rd = (ps.flags & PF_FIRST_BWD) ? 1 : 3;
+        if (!ws || ws_bytes < qsv_workspace_size(p, B, QSV_OP_BACKWARD)) {
+            set_error("pass copy: backward workspace too small");
+            return QSV_ERR_ARG;
+        }
+        char* c = (char*)ws + mats_bytes(p, B);
+        float2* psi = (float2*)c;
+        float2* lam = (float2*)(c + align256(state_bytes(p, B)) + kLamSkew);
+        const bool first = ps.flags & PF_FIRST_BWD;
+        rd = first ? 1 : 3;
         wr = (ps.flags & PF_LAST_BWD) ? 0 : 3;
+        ra = first ? (float2*)d_state : psi;
+        rb = lam;
+        wa = psi;
+        wb = lam;
     }
-    if (!d_a || (((rd | wr) & 2) && !d_b)) { set_error("pass copy: null array"); return QSV_ERR_ARG; }
-    const int m = ps.m;
     const bool pair = ps.lq[0] == 0;
     const uintptr_t al = pair ? 15 : 7;
-    if (((uintptr_t)d_a & al) || (d_b && ((uintptr_t)d_b & al))) {
+    if (((uintptr_t)ra & al) || ((uintptr_t)rb & al) || ((uintptr_t)wa & al) || ((uintptr_t)wb & al)) {
         set_error("pass copy: arrays must be 16-byte aligned");
         return QSV_ERR_ARG;
     }
-    if (m < kRegBits + 1 || m > p->W) { set_error("pass copy: tile too small"); return QSV_ERR_ARG; }
-    if (lds_bytes < 0 || lds_bytes > 65536) { set_error("pass copy: lds_bytes outside 0..65536"); return QSV_ERR_ARG; }
     PassGeom g{};
     g.m = m;
     g.W = p->W;
@@ -3055,7 +3074,7 @@ int qsv_pass_copy(const qsv_plan_t* p, int32_t which, int32_t pass, int64_t B, v
     const uint64_t tiles = (uint64_t)B << g.tb;
     const int threads = std::max(64, 1 << (m - kRegBits));
     hipLaunchKernelGGL(k_pass_copy, dim3((unsigned)tiles), dim3(threads), (size_t)lds_bytes, (hipStream_t)stream,
-                       (float2*)d_a, (float2*)d_b, g, rd, wr);
+                       (const float2*)ra, (const float2*)rb, wa, wb, g, rd, wr);
     HIP_TRY(hipGetLastError());
     return QSV_OK;
 }

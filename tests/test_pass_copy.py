@@ -22,18 +22,20 @@ def test_pass_copy_rejects_bad_calls_before_any_device_work():
     fake = 256  # never dereferenced: every call below returns before a launch
     c = inputs.ry_rz_cnot_ring(12, 2)
     pg = _plan(c, method="per_gate")
-    assert L.qsv_pass_copy(pg.handle, 0, 0, 2, fake, fake, 0, None) == -1
+    assert L.qsv_pass_copy(pg.handle, 0, 0, 2, fake, None, 0, 0, None) == -1
     assert b"fused" in L.qsv_last_error()
     p = _plan(c, method="fused", tile_qubits=8)
     info = p.info()
-    assert L.qsv_pass_copy(p.handle, 2, 0, 2, fake, fake, 0, None) == -1
-    assert L.qsv_pass_copy(p.handle, 0, info["n_fwd_passes"], 2, fake, fake, 0, None) == -1
-    assert L.qsv_pass_copy(p.handle, 1, -1, 2, fake, fake, 0, None) == -1
-    assert L.qsv_pass_copy(p.handle, 0, 0, 0, fake, fake, 0, None) == -1
-    assert L.qsv_pass_copy(p.handle, 0, 1, 2, None, None, 0, None) == -1
-    assert L.qsv_pass_copy(p.handle, 1, 1, 2, fake, None, 0, None) == -1  # a backward pass needs lambda
-    assert L.qsv_pass_copy(p.handle, 0, 1, 2, fake + 4, None, 0, None) == -1  # misaligned
-    assert L.qsv_pass_copy(p.handle, 0, 1, 2, fake, None, 65537, None) == -1  # LDS beyond 64 KiB
+    need = binding.qsv_workspace_size(p.handle, 2, binding.OP_BACKWARD)
+    assert L.qsv_pass_copy(p.handle, 2, 0, 2, fake, fake, need, 0, None) == -1
+    assert L.qsv_pass_copy(p.handle, 0, info["n_fwd_passes"], 2, fake, None, 0, 0, None) == -1
+    assert L.qsv_pass_copy(p.handle, 1, -1, 2, fake, fake, need, 0, None) == -1
+    assert L.qsv_pass_copy(p.handle, 0, 0, 0, fake, None, 0, 0, None) == -1
+    assert L.qsv_pass_copy(p.handle, 0, 1, 2, None, None, 0, 0, None) == -1
+    assert L.qsv_pass_copy(p.handle, 1, 1, 2, fake, None, 0, 0, None) == -1  # a backward pass needs the workspace
+    assert L.qsv_pass_copy(p.handle, 1, 1, 2, fake, fake, need - 1, 0, None) == -1
+    assert L.qsv_pass_copy(p.handle, 0, 1, 2, fake + 4, None, 0, 0, None) == -1  # misaligned
+    assert L.qsv_pass_copy(p.handle, 0, 1, 2, fake, None, 0, 65537, None) == -1  # LDS beyond 64 KiB
 
 
 CASES = [
@@ -43,6 +45,11 @@ CASES = [
     ("ring14_t10", lambda: inputs.ry_rz_cnot_ring(14, 3), {"tile_qubits": 10}),
     ("ladder13_t9_low0", lambda: inputs.rx_ry_rz_cz_ladder(13, 2), {"tile_qubits": 9, "low_qubits": 0}),
 ]
+
+# Where qsv_backward keeps psi and lambda in its workspace: psi right after the
+# gate matrices (the forward workspace), lambda 4 KiB + 256 bytes past the end of
+# psi's 256-byte-aligned extent.
+LAMBDA_SKEW = 4096 + 256
 
 
 @pytest.mark.gpu
@@ -60,24 +67,30 @@ def test_pass_copy_touches_each_amplitude_once(name, make, opts):
     ref_a = torch.randn((B, n), dtype=torch.complex64, generator=g)
     ref_b = torch.randn((B, n), dtype=torch.complex64, generator=g)
     nan = torch.full((B, n), complex(float("nan"), float("nan")), dtype=torch.complex64)
-    assert info["n_bwd_passes"] > 1  # the first backward pass then writes lambda
-    for which, count in ((0, info["n_fwd_passes"]), (1, info["n_bwd_passes"])):
-        for i in range(count):
-            print(f"[pass_copy] {name} which={which} pass={i}", flush=True)
-            first = i == 0
-            a = (nan if (which == 0 and first) else ref_a).to(dev)
-            b = (nan if (which == 1 and first) else ref_b).to(dev)
-            p.pass_copy(which, i, B, a, b, lds_bytes=(0, 40960)[i % 2])
-            torch.cuda.synchronize()
-            a, b = a.cpu(), b.cpu()
-            if which == 0 and first:
-                assert torch.equal(a, torch.zeros_like(a))
-            else:
-                assert torch.equal(a, ref_a)
-            if which == 1:
-                if first:
-                    assert torch.equal(b, ref_a)
-                else:
-                    assert torch.equal(b, ref_b)
-            else:
-                assert torch.equal(b, ref_b)
+    ws = p.workspace(B, binding.OP_BACKWARD, dev)
+    mats = binding.qsv_workspace_size(p.handle, B, binding.OP_FORWARD)
+    nbytes = B * n * 8
+    psi = ws[mats:mats + nbytes].view(torch.complex64).view(B, n)
+    lo = mats + (nbytes + 255) // 256 * 256 + LAMBDA_SKEW
+    lam = ws[lo:lo + nbytes].view(torch.complex64).view(B, n)
+    assert info["n_bwd_passes"] > 1  # the first backward pass then writes psi and lambda
+    for i in range(info["n_fwd_passes"]):
+        print(f"[pass_copy] {name} forward pass {i}", flush=True)
+        st = (nan if i == 0 else ref_a).to(dev)
+        p.pass_copy(0, i, B, st, lds_bytes=(0, 40960)[i % 2])
+        torch.cuda.synchronize()
+        assert torch.equal(st.cpu(), torch.zeros_like(ref_a) if i == 0 else ref_a)
+    for i in range(info["n_bwd_passes"]):
+        print(f"[pass_copy] {name} backward pass {i}", flush=True)
+        st = ref_a.to(dev)
+        if i == 0:
+            psi.copy_(nan.to(dev))
+            lam.copy_(nan.to(dev))
+        else:
+            psi.copy_(ref_a.to(dev))
+            lam.copy_(ref_b.to(dev))
+        p.pass_copy(1, i, B, st, lds_bytes=(0, 40960)[i % 2])
+        torch.cuda.synchronize()
+        assert torch.equal(st.cpu(), ref_a)
+        assert torch.equal(psi.cpu(), ref_a)
+        assert torch.equal(lam.cpu(), ref_a if i == 0 else ref_b)
