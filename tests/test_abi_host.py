@@ -390,3 +390,27 @@ def test_codegen_source_empty_for_per_gate(lib):
     c = I.rx_ry_rz_cz_ladder(6, 1)
     p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="per_gate")
     assert B.qsv_plan_codegen_source(p.handle) == ""
+
+
+def test_parity_plans_cover_every_form_of_control_condition(lib):
+    """The generated kernels test a control outside the registers in three ways:
+    a swap under a lane-bit control as selects, a wave-uniform control as a
+    branch on a value read from the first lane, and any other lane-bit control
+    as a per-lane branch. The plans of the GPU parity tests with controlled
+    gates on small tiles (tests/test_gpu_parity.py::test_controlled_kinds_small_tiles)
+    and of the 16-qubit ring at full size must between them emit all three, so
+    that parity covers each."""
+    srcs = []
+    for W, m, cq in [(9, 4, 1), (11, 6, 2), (13, 8, 3)]:
+        rng = np.random.default_rng(100 + W)
+        c = I.random_mixed(W, 120, rng, n_inputs=2, p_input=0.3, kinds=I.ALL_KINDS)
+        p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="fused", codegen=1,
+                   tile_qubits=m, low_qubits=cq)
+        srcs.append(B.qsv_plan_codegen_source(p.handle))
+    c, batch, seed = I.workload("w16_b256_ring")
+    p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="fused")
+    srcs.append(B.qsv_plan_codegen_source(p.handle))
+    src = "\n".join(srcs)
+    assert "const bool c_ = ((gT >>" in src                      # lane-bit swap as selects
+    assert "if (__builtin_amdgcn_readfirstlane((int)(" in src     # wave-uniform branch
+    assert re.search(r"^    if \(\(\(gT >> \d+\) & 1\)", src, re.M)  # lane-bit branch
