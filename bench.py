@@ -208,6 +208,16 @@ def step_spread(ms_list):
             "std": round(statistics.pstdev(ms_list), 4) if len(ms_list) > 1 else 0.0}
 
 
+def opts_summary(opts):
+    """Tuned options as reported: the option dict, or for options chosen per
+    circuit how many circuits took each option set."""
+    if "per_circuit" not in opts:
+        return opts
+    import collections
+    cnt = collections.Counter(json.dumps(o, sort_keys=True) for o in opts["per_circuit"])
+    return {"per_circuit": [{"opts": json.loads(k), "circuits": n} for k, n in cnt.most_common()]}
+
+
 def bench_uneven(args, torch, dev, binding, inputs):
     """512 circuits of 8..18 qubits and 2..12 random layers, batch 1 each, in
     one multi-circuit plan: options from the tuner, the whole step (forward +
@@ -271,7 +281,7 @@ def bench_uneven(args, torch, dev, binding, inputs):
            "evals_per_s": round(len(cs) / (gms / 1e3), 1), "ms_per_step": round(gms, 4),
            "eager_ms_per_step": round(ems, 4),
            "alg_gbs": round(step_bytes / (gms / 1e3) / 1e9, 1),
-           "opts": tr["opts"], "tune_seconds": tr["seconds"], "plan_ms": round(plan_ms, 1),
+           "opts": opts_summary(tr["opts"]), "tune_seconds": tr["seconds"], "plan_ms": round(plan_ms, 1),
            "graph_equals_eager": same,
            "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3)}
                        for k, v in stats.items()}}

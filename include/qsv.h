@@ -237,6 +237,19 @@ int qsv_plan(int32_t n_qubits, const qsv_gate* gates, int32_t n_gates, int32_t n
 int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* opts,
                    qsv_plan_t** out);
 
+/*
+ * qsv_plan_multi with options chosen per circuit: circuit c is split and
+ * scheduled with per_circuit[c] (n_circuits entries, host memory, read during
+ * the call only; the same fields and limits as the options of qsv_plan_multi),
+ * so that a batch of unrelated circuits can take the fusion width, tile and
+ * low qubits that suit each (section "Circuit Splitting" leaves the block
+ * size to the user). weight_remap must be the same for every circuit;
+ * qsv_plan_get_info reports the options of circuit 0. Layouts, launches and
+ * results are as with qsv_plan_multi.
+ */
+int qsv_plan_multi_each(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* per_circuit,
+                        qsv_plan_t** out);
+
 /* Offsets of circuit `circuit` in the layouts above (single plans: all 0).
  * Any output pointer may be NULL. */
 int qsv_plan_circuit_offsets(const qsv_plan_t* plan, int32_t circuit, int64_t* amp_offset,

@@ -72,7 +72,8 @@ class qsv_kernel_stat(ctypes.Structure):
                 ("flops", ctypes.c_double)]
 
 
-EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_circuit_offsets", "qsv_state_offset",
+EXPORTS = ("qsv_default_opts", "qsv_plan", "qsv_plan_multi", "qsv_plan_multi_each", "qsv_plan_circuit_offsets",
+           "qsv_state_offset",
            "qsv_plan_multi_items", "qsv_plan_destroy", "qsv_workspace_size",
            "qsv_forward", "qsv_expval", "qsv_forward_expval", "qsv_forward_expval_noalloc",
            "qsv_backward", "qsv_plan_get_info",
@@ -109,6 +110,9 @@ def lib():
         L.qsv_plan_multi.argtypes = [ctypes.POINTER(qsv_circuit), i32, ctypes.POINTER(qsv_opts),
                                      ctypes.POINTER(vp)]
         L.qsv_plan_multi.restype = ctypes.c_int
+        L.qsv_plan_multi_each.argtypes = [ctypes.POINTER(qsv_circuit), i32, ctypes.POINTER(qsv_opts),
+                                          ctypes.POINTER(vp)]
+        L.qsv_plan_multi_each.restype = ctypes.c_int
         L.qsv_plan_circuit_offsets.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                                ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.qsv_plan_circuit_offsets.restype = ctypes.c_int
@@ -200,16 +204,30 @@ def _gate_array(gates):
     return arr
 
 
-def qsv_plan_multi(circuits, opts=None):
-    """circuits: sequence of (n_qubits, gates, n_weights, n_inputs)."""
+def _circuit_array(circuits):
     keep = [_gate_array(g) for (_, g, _, _) in circuits]
     arr = (qsv_circuit * len(circuits))()
     for i, (n, g, nw, ni) in enumerate(circuits):
         arr[i] = qsv_circuit(int(n), len(g), ctypes.cast(keep[i], ctypes.POINTER(qsv_gate)),
                              int(nw), int(ni))
+    return arr, keep
+
+
+def qsv_plan_multi(circuits, opts=None):
+    """circuits: sequence of (n_qubits, gates, n_weights, n_inputs)."""
+    arr, keep = _circuit_array(circuits)
     h = ctypes.c_void_p()
     _check(lib().qsv_plan_multi(arr, len(circuits), ctypes.byref(opts) if opts is not None else None,
                                 ctypes.byref(h)))
+    return h
+
+
+def qsv_plan_multi_each(circuits, per_circuit):
+    """circuits as for qsv_plan_multi; per_circuit: one qsv_opts per circuit."""
+    arr, keep = _circuit_array(circuits)
+    opts = (qsv_opts * len(circuits))(*per_circuit)
+    h = ctypes.c_void_p()
+    _check(lib().qsv_plan_multi_each(arr, len(circuits), opts, ctypes.byref(h)))
     return h
 
 
@@ -543,10 +561,17 @@ class MultiPlan(Plan):
     n_weights, n_inputs). Layouts are documented with qsv_plan_multi.
     """
 
-    def __init__(self, circuits, **opts):
+    def __init__(self, circuits, per_circuit=None, **opts):
+        """per_circuit: optional list of option dicts, one per circuit (each
+        completed by `opts` and the defaults): qsv_plan_multi_each."""
         self.opts = make_opts(**opts)
         spec = [(c.n_qubits, c.gates, c.n_weights, c.n_inputs) for c in circuits]
-        self.handle = qsv_plan_multi(spec, self.opts)
+        if per_circuit is None:
+            self.handle = qsv_plan_multi(spec, self.opts)
+        else:
+            if len(per_circuit) != len(spec):
+                raise ValueError("per_circuit needs one option set per circuit")
+            self.handle = qsv_plan_multi_each(spec, [make_opts(**{**opts, **o}) for o in per_circuit])
         self.n_circuits = len(spec)
         self.n_gates = sum(len(c[1]) for c in spec)
         self.n_weights = sum(c[2] for c in spec)

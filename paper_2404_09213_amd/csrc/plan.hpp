@@ -255,7 +255,7 @@ inline int64_t pg_chunks(int W) {
     return q / 1024 > 1 ? q / 1024 : 1;
 }
 int build_plan(qsv_plan_t* p);  // planner.cpp
-struct CircuitIn { int W; const qsv_gate* gates; int n_gates, n_weights, n_inputs; };
+struct CircuitIn { int W; const qsv_gate* gates; int n_gates, n_weights, n_inputs; qsv_opts opts; };
 int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs);  // planner.cpp
 void set_error(const std::string& msg);       // api
 }  // namespace qsv

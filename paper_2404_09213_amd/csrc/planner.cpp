@@ -1031,7 +1031,7 @@ int build_multi(qsv_plan_t* p, const std::vector<CircuitIn>& cs) {
         sub.n_gates = ci.n_gates;
         sub.n_weights = ci.n_weights;
         sub.n_inputs = ci.n_inputs;
-        sub.opts = p->opts;
+        sub.opts = ci.opts;  // each circuit's own options (validated by the caller)
         sub.opts.method = QSV_METHOD_FUSED;
         sub.opts.codegen = 0;
         sub.opts.tile_qubits = std::min(sub.opts.tile_qubits, (int32_t)kMaxTileQubitsTables);

@@ -2763,15 +2763,8 @@ int qsv_backward(const qsv_plan_t* p, const float* w, const float* x, int64_t B,
     return QSV_OK;
 }
 
-int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* opts,
-                   qsv_plan_t** out) {
-    TraceRange trace_("qsv_plan_multi");
-    if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
-    *out = nullptr;
-    if (!circuits || n_circuits < 1) { set_error("need at least one circuit"); return QSV_ERR_ARG; }
-    qsv_opts o;
-    qsv_default_opts(&o);
-    if (opts) o = *opts;
+// Options of one circuit of a multi-circuit plan, completed and checked.
+static int multi_opts(qsv_opts& o) {
     o.method = QSV_METHOD_FUSED;
     o.codegen = 0;
     if (o.fuse_width < 1 || o.fuse_width > 16) { set_error("fuse_width must be in 1..16"); return QSV_ERR_ARG; }
@@ -2784,6 +2777,12 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     if (o.splitter != 0 && o.splitter != 1) { set_error("splitter must be 0 or 1"); return QSV_ERR_ARG; }
     if (o.pack_beam < 0 || o.pack_beam > 256) { set_error("pack_beam must be in 0..256"); return QSV_ERR_ARG; }
     if (o.amp_dtype != QSV_AMP_C64) { set_error("multi-circuit plans use complex64 amplitudes (amp_dtype = 0)"); return QSV_ERR_ARG; }
+    return QSV_OK;
+}
+
+// A multi-circuit plan from circuits and one completed option set per circuit.
+static int plan_multi(const qsv_circuit* circuits, int32_t n_circuits, std::vector<qsv_opts>& per,
+                      qsv_plan_t** out) {
     std::vector<CircuitIn> cs;
     int64_t row = 0;
     for (int c = 0; c < n_circuits; ++c) {
@@ -2791,17 +2790,17 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
         if (C.n_qubits < kRegBits) { set_error("multi-circuit plans need circuits of at least 4 qubits"); return QSV_ERR_ARG; }
         // validate each circuit like a single plan (host only)
         qsv_plan_t* tmp = nullptr;
-        qsv_opts ot = o;
+        qsv_opts ot = per[c];
         int rc = qsv_plan(C.n_qubits, C.gates, C.n_gates, C.n_weights, C.n_inputs, &ot, &tmp);
         if (rc) return rc;
         qsv_plan_destroy(tmp);
         row += int64_t(1) << C.n_qubits;
-        cs.push_back({C.n_qubits, C.gates, C.n_gates, C.n_weights, C.n_inputs});
+        cs.push_back({C.n_qubits, C.gates, C.n_gates, C.n_weights, C.n_inputs, per[c]});
     }
     if (row > (int64_t(1) << 34)) { set_error("circuits too large together"); return QSV_ERR_TOO_BIG; }
     qsv_plan_t* p = new (std::nothrow) qsv_plan_t();
     if (!p) { set_error("plan allocation failed"); return QSV_ERR_OOM; }
-    p->opts = o;
+    p->opts = per[0];  // plan-wide settings (weight remapping) and what qsv_plan_get_info reports
     int W = 0;
     for (auto& c : cs) W = std::max(W, c.W);
     p->W = W;
@@ -2819,6 +2818,40 @@ int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_op
     handle_add(g_live_plans, p);
     *out = p;
     return QSV_OK;
+}
+
+int qsv_plan_multi(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* opts,
+                   qsv_plan_t** out) {
+    TraceRange trace_("qsv_plan_multi");
+    if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
+    *out = nullptr;
+    if (!circuits || n_circuits < 1) { set_error("need at least one circuit"); return QSV_ERR_ARG; }
+    qsv_opts o;
+    qsv_default_opts(&o);
+    if (opts) o = *opts;
+    int rc = multi_opts(o);
+    if (rc) return rc;
+    std::vector<qsv_opts> per((size_t)n_circuits, o);
+    return plan_multi(circuits, n_circuits, per, out);
+}
+
+int qsv_plan_multi_each(const qsv_circuit* circuits, int32_t n_circuits, const qsv_opts* per_circuit,
+                        qsv_plan_t** out) {
+    TraceRange trace_("qsv_plan_multi_each");
+    if (!out) { set_error("out is NULL"); return QSV_ERR_ARG; }
+    *out = nullptr;
+    if (!circuits || n_circuits < 1) { set_error("need at least one circuit"); return QSV_ERR_ARG; }
+    if (!per_circuit) { set_error("per_circuit is NULL"); return QSV_ERR_ARG; }
+    std::vector<qsv_opts> per(per_circuit, per_circuit + n_circuits);
+    for (qsv_opts& o : per) {
+        int rc = multi_opts(o);
+        if (rc) return rc;
+        if (o.weight_remap != per[0].weight_remap) {
+            set_error("weight_remap must be the same for every circuit");
+            return QSV_ERR_ARG;
+        }
+    }
+    return plan_multi(circuits, n_circuits, per, out);
 }
 
 int qsv_plan_circuit_offsets(const qsv_plan_t* p, int32_t circuit, int64_t* amp, int32_t* qubit,

@@ -5,7 +5,9 @@ small widths) and notes that the split is made once, when the circuit is
 built. Here the choice is made once per (circuit, batch, device): every
 candidate plan is built on the host and ranked by the library's cost model
 (qsv_plan_estimate); the best few are then timed on the device (one full
-step each: forward + readout + adjoint backward) and the fastest wins. Results
+step each: forward + readout + adjoint backward) and the fastest wins. For
+many circuits in one plan, one more timed candidate gives every circuit the
+options the model ranks best for it alone (qsv_plan_multi_each). Results
 are kept in a JSON file (path from the `cache` argument or the QSV_TUNE_CACHE
 environment variable) keyed by a hash of the gate lists, the batch and the
 device architecture, so later runs skip the timing.
@@ -41,6 +43,39 @@ def default_space(circuits, multi):
             "splitter": [0, 1]}
 
 
+def per_circuit_choice(circuits, batch, space, threads=None):
+    """Options of each circuit of a multi-circuit plan by the cost model alone:
+    the candidate of `space` with the lowest estimate for a single plan of that
+    circuit (launch costs left out: the circuits share their launches).
+    Planning runs in the library, outside the interpreter lock, so the
+    circuits are spread over a few threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    names = sorted(space)
+    combos = [dict(zip(names, v)) for v in itertools.product(*(space[n] for n in names))]
+    combos = [o for o in combos if o.get("low_qubits", 0) < o.get("tile_qubits", 99)]
+
+    def best(c):
+        top = None
+        seen = set()
+        for o in combos:
+            # tiles at least as wide as the circuit all clamp to its width
+            key = tuple(sorted({**o, "tile_qubits": min(o.get("tile_qubits", 12), c.n_qubits)}.items()))
+            if key in seen:
+                continue
+            seen.add(key)
+            p = binding.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="fused", codegen=0, **o)
+            e = binding.qsv_plan_estimate(p.handle, batch, HBM_GBS, ALU_TFLOPS, 0.0)
+            del p
+            if top is None or e < top[0]:
+                top = (e, o)
+        return top[1]
+
+    if threads is None:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(best, circuits))
+
+
 def _make(circuits, multi, opts):
     if multi:
         return binding.MultiPlan(circuits, **opts)
@@ -71,13 +106,16 @@ def _time_step(plan, batch, steps, torch, dev):
 
 
 def tune(circuits, batch, *, multi=None, space=None, top=4, steps=3, cache=None, device="cuda:0",
-         log=None):
+         log=None, per_circuit=True):
     """Pick fuse_width / tile_qubits / low_qubits for `circuits` at `batch`.
 
     circuits: one Circuit or a list (a list of more than one means a
-    multi-circuit plan unless multi=False). Returns a dict with the chosen
-    options ("opts"), the model's estimate and the measured step time of
-    every timed candidate ("timed"), and whether it came from the cache.
+    multi-circuit plan unless multi=False). For a multi-circuit plan the timed
+    candidates also include options chosen per circuit by the model
+    (per_circuit_choice; opts = {"per_circuit": [one dict per circuit]}, for
+    MultiPlan). Returns a dict with the chosen options ("opts"), the model's
+    estimate and the measured step time of every timed candidate ("timed"),
+    and whether it came from the cache.
     """
     import torch
     if not isinstance(circuits, (list, tuple)):
@@ -128,6 +166,19 @@ def tune(circuits, batch, *, multi=None, space=None, top=4, steps=3, cache=None,
         plan = _make(circuits, multi, dflt)
         pick.append((binding.qsv_plan_estimate(plan.handle, batch, HBM_GBS, ALU_TFLOPS, LAUNCH_US), dflt))
         del plan
+    if multi and per_circuit:
+        # one more candidate: every circuit with the options the model ranks best
+        # for it, at the widest tile of the space (the multi-circuit kernels run
+        # 256 threads per item whatever the tile, so narrower tiles leave lanes idle)
+        t1 = time.perf_counter()
+        pc_space = dict(space)
+        if "tile_qubits" in pc_space:
+            pc_space["tile_qubits"] = [max(pc_space["tile_qubits"])]
+        opts = {"per_circuit": per_circuit_choice(circuits, batch, pc_space)}
+        plan = _make(circuits, multi, opts)
+        pick.append((binding.qsv_plan_estimate(plan.handle, batch, HBM_GBS, ALU_TFLOPS, LAUNCH_US), opts))
+        del plan
+        host_s += time.perf_counter() - t1
 
     timed = []
     for est, opts in pick:
@@ -135,7 +186,8 @@ def tune(circuits, batch, *, multi=None, space=None, top=4, steps=3, cache=None,
         ms = _time_step(plan, batch, steps, torch, dev)
         timed.append({"opts": opts, "est_ms": round(est / 1e3, 4), "ms": round(ms, 4)})
         if log:
-            log(f"[tune] {opts} est={est / 1e3:.3f} ms measured={ms:.3f} ms")
+            shown = "per circuit" if "per_circuit" in opts else opts
+            log(f"[tune] {shown} est={est / 1e3:.3f} ms measured={ms:.3f} ms")
         del plan
     best = min(timed, key=lambda r: r["ms"])
     out = {"opts": best["opts"], "ms": best["ms"], "timed": timed, "n_candidates": len(ranked),

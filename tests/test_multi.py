@@ -80,6 +80,57 @@ def test_multi_plan_rejects_small_and_invalid():
     assert e.value.code == -2
 
 
+def _per_circuit_options(cs, seed):
+    """Options varied per circuit: fusion width 1-3, tiles of 4-12 qubits (at
+    most the circuit's width), low qubits below the tile, both splitters."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in cs:
+        m = int(rng.integers(4, min(12, c.n_qubits) + 1))
+        out.append({"fuse_width": int(rng.integers(1, 4)), "tile_qubits": m,
+                    "low_qubits": int(rng.integers(0, m)), "splitter": int(rng.integers(0, 2))})
+    return out
+
+
+def test_multi_each_with_equal_options_is_the_multi_plan():
+    cs = _mixed_set(3, 6, 4, 12)
+    o = {"fuse_width": 2, "tile_qubits": 8, "low_qubits": 3}
+    a = B.MultiPlan(cs, **o)
+    b = B.MultiPlan(cs, per_circuit=[o] * len(cs))
+    assert a.info() == b.info()
+    assert np.array_equal(a.gate_order(0), b.gate_order(0)) and np.array_equal(a.gate_order(1), b.gate_order(1))
+    for which in (0, 1):
+        assert np.array_equal(B.qsv_plan_multi_items(a.handle, 2, which), B.qsv_plan_multi_items(b.handle, 2, which))
+
+
+def test_multi_each_plans_every_circuit_with_its_own_options():
+    cs = _mixed_set(4, 8, 5, 14)
+    per = _per_circuit_options(cs, 4)
+    mp = B.MultiPlan(cs, per_circuit=per)
+    items = B.qsv_plan_multi_items(mp.handle, 1, 0)
+    for i, (c, o) in enumerate(zip(cs, per)):
+        # a circuit's pass-0 items are its tiles: 2^(n - m) with m its own tile width
+        tiles = {int(t) for (ci, r, t) in items if ci == i and r == 0}
+        assert tiles == set(range(1 << (c.n_qubits - min(o["tile_qubits"], c.n_qubits)))), i
+        # the same schedule as a single plan of that circuit with those options
+        single = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="fused", codegen=0, **o)
+        n_fwd = len({int(r) for (ci, r, t) in items if ci == i})
+        assert n_fwd == single.info()["n_fwd_passes"], i
+
+
+def test_multi_each_rejects_bad_options():
+    cs = _mixed_set(5, 3, 5, 9)
+    with pytest.raises(ValueError):
+        B.MultiPlan(cs, per_circuit=[{}] * 2)
+    with pytest.raises(B.QsvError) as e:
+        B.MultiPlan(cs, per_circuit=[{"weight_remap": 1}, {}, {}])
+    assert e.value.code == -1 and b"weight_remap" in B.lib().qsv_last_error()
+    with pytest.raises(B.QsvError):
+        B.MultiPlan(cs, per_circuit=[{}, {"tile_qubits": 13}, {}])
+    with pytest.raises(B.QsvError):
+        B.MultiPlan(cs, per_circuit=[{}, {}, {"low_qubits": 12, "tile_qubits": 12}])
+
+
 def test_uneven_set_shape():
     cs = I.uneven_set(512)
     ns = [c.n_qubits for c in cs]
@@ -220,6 +271,12 @@ def test_multi_controlled_kinds(orc):
 @pytest.mark.gpu
 def test_multi_weight_remap(orc):
     _run_multi(_mixed_set(12, 5, 4, 11), 2, 12, orc, weight_remap=1)
+
+
+@pytest.mark.gpu
+def test_multi_each_options_per_circuit(orc):
+    cs = _mixed_set(14, 9, 4, 13)
+    _run_multi(cs, 2, 14, orc, per_circuit=_per_circuit_options(cs, 14))
 
 
 @pytest.mark.gpu

@@ -1,4 +1,5 @@
 """Cost model (host) and option tuner (device)."""
+import itertools
 import json
 
 import numpy as np
@@ -61,3 +62,32 @@ def test_tune_picks_timed_best_and_caches(tmp_path):
         assert len(json.load(f)) == 1
     r2 = tune.tune(c, 16, space=space, top=2, steps=2, cache=path)
     assert r2["cached"] and r2["opts"] == r["opts"]
+
+
+def test_per_circuit_choice_never_estimates_worse_than_one_global_choice():
+    # The multi estimate without launch costs is the sum over circuits, so
+    # choosing each circuit's options by its own estimate can only lower it.
+    from paper_2404_09213_amd import tune
+    cs = I.uneven_set(24, seed=77)
+    space = {"fuse_width": [1, 2, 3], "tile_qubits": [10, 12], "low_qubits": [3, 4], "splitter": [0, 1]}
+    per = tune.per_circuit_choice(cs, 1, space, threads=4)
+    assert len(per) == len(cs) and all(set(o) == set(space) for o in per)
+    mp = B.MultiPlan(cs, per_circuit=per)
+    e_per = B.qsv_plan_estimate(mp.handle, 1, tune.HBM_GBS, tune.ALU_TFLOPS, 0.0)
+    names = sorted(space)
+    for vals in itertools.product(*(space[n] for n in names)):
+        o = dict(zip(names, vals))
+        mg = B.MultiPlan(cs, **o)
+        e = B.qsv_plan_estimate(mg.handle, 1, tune.HBM_GBS, tune.ALU_TFLOPS, 0.0)
+        assert e_per <= e * (1 + 1e-12), o
+
+
+@pytest.mark.gpu
+def test_tune_multi_times_a_per_circuit_candidate(tmp_path):
+    from paper_2404_09213_amd import tune
+    print("tune 12 mixed circuits with a per-circuit candidate", flush=True)
+    cs = I.uneven_set(12, seed=78, qmax=14)
+    space = {"fuse_width": [1, 2], "tile_qubits": [10, 12], "low_qubits": [4]}
+    r = tune.tune(cs, 1, multi=True, space=space, top=1, steps=2, cache=str(tmp_path / "t.json"))
+    assert any("per_circuit" in t["opts"] for t in r["timed"])
+    assert r["ms"] == min(t["ms"] for t in r["timed"])
