@@ -139,7 +139,7 @@ def test_product_state_closed_form_w20(method):
     assert np.abs(got["gw"].cpu().numpy() - gw).max() < 1e-4 * np.abs(gw).max()
 
 
-def _sampled_full_size(orc, name, method, samples):
+def _sampled_full_size(orc, name, method, samples, **extra):
     """Full-size workload in the benchmark's launch configuration; the oracle
     recomputes selected samples one by one. Weight gradients are linear in the
     upstream gradient g, so zeroing g outside the selected samples makes the
@@ -148,8 +148,8 @@ def _sampled_full_size(orc, name, method, samples):
     w, x = I.draw_angles(c, batch, seed)
     g = np.zeros((batch, c.n_qubits))
     g[samples] = I.draw_grad_out(c, batch, seed)[samples]
-    print(f"[parity] {name} sampled {samples} method={method}", flush=True)
-    got = gpu_run(c, w, x, batch, g, **_opts(method))
+    print(f"[parity] {name} sampled {samples} method={method} {extra}", flush=True)
+    got = gpu_run(c, w, x, batch, g, **_opts(method, **extra))
     ref = oracle_run(orc, c, w, x[samples], len(samples), g[samples])
     st = got["state"].cpu().numpy()[samples]
     assert np.abs(st - ref["state"]).max() <= AMP_TOL
@@ -172,6 +172,12 @@ def test_full_size_w20_b64_sampled(orc, method):
 @pytest.mark.parametrize("method", METHODS)
 def test_full_size_w16_b256_sampled(orc, method):
     _sampled_full_size(orc, "w16_b256_ring", method, [0, 101, 255])
+
+
+@pytest.mark.parametrize("method", ["fused", "fused_tables"])
+def test_full_size_w16_b256_blocks_of_5_sampled(orc, method):
+    # the 16-qubit workload as specified: split into blocks of up to 5 qubits
+    _sampled_full_size(orc, "w16_b256_ring", method, [3, 200], fuse_width=5)
 
 
 @pytest.mark.parametrize("method", METHODS)
