@@ -131,7 +131,11 @@ def log(args, *a):
 
 
 def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
-    """Warm up, then time `steps` steps; returns (ms_per_step, per-kernel stats, per-step ms)."""
+    """Warm up, then time `steps` steps without instrumentation (the step time),
+    then the same steps again with the library's HIP events around every
+    launch (per-kernel durations, algorithmic bytes and flops): the events add
+    a few microseconds per launch, which would otherwise count in the step.
+    Returns (ms_per_step, per-kernel stats, per-step ms)."""
     B = state.shape[0]
     n = len(ws_inputs)
 
@@ -142,9 +146,6 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
 
     for r in range(warmup):
         step(r)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read()  # drop anything recorded before the timed region
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
@@ -155,6 +156,11 @@ def run_steps(plan, ws_inputs, g, state, E, gw, gx, steps, warmup, torch):
     torch.cuda.synchronize()
     total_ms = ev[0].elapsed_time(ev[-1])
     step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    plan.profile(True)
+    plan.profile_read()  # drop anything recorded before
+    for r in range(warmup, warmup + steps):
+        step(r)
+    torch.cuda.synchronize()
     stats = plan.profile_read()
     plan.profile(False)
     return total_ms / steps, stats, step_ms
