@@ -739,6 +739,7 @@ private:
                 }
             }
         }
+        lay_ = nullptr;  // cur goes out of scope with this kernel
         const bool write_back = !bwd_ || !(flags & PF_LAST_BWD);
         if (write_back) {
             if (!same(cur, nat)) {
