@@ -3080,7 +3080,7 @@ int qsv_pass_copy(const qsv_plan_t* p, int32_t which, int32_t pass, int64_t B, v
     if (lds_bytes < 0 || lds_bytes > 65536) { set_error("pass copy: lds_bytes outside 0..65536"); return QSV_ERR_ARG; }
     const DPass& ps = passes[pass];
     const int m = ps.m;
-    if (m < kRegBits + 1 || m > p->W) { set_error("pass copy: tile too small"); return QSV_ERR_ARG; }
+    if (m < kRegBits || m > p->W) { set_error("pass copy: tile outside 4..n qubits"); return QSV_ERR_ARG; }
     if (!d_state) { set_error("pass copy: null state"); return QSV_ERR_ARG; }
     // the arrays the pass itself reads and writes: the state (forward, and
     // psi_N for the first backward pass), psi and lambda in the backward workspace

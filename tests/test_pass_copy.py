@@ -39,11 +39,12 @@ def test_pass_copy_rejects_bad_calls_before_any_device_work():
 
 
 CASES = [
-    # (name, circuit, options): tiles of 8 and 10 qubits over 12-14-qubit states,
-    # with 4 low qubits (16-byte pairs) and with none (single amplitudes)
+    # (name, circuit, options): tiles of 4 to 10 qubits over 9-14-qubit states,
+    # with low qubits (16-byte pairs) and with none (single amplitudes)
     ("ring12_t8", lambda: inputs.ry_rz_cnot_ring(12, 3), {"tile_qubits": 8}),
     ("ring14_t10", lambda: inputs.ry_rz_cnot_ring(14, 3), {"tile_qubits": 10}),
     ("ladder13_t9_low0", lambda: inputs.rx_ry_rz_cz_ladder(13, 2), {"tile_qubits": 9, "low_qubits": 0}),
+    ("ring9_t4", lambda: inputs.ry_rz_cnot_ring(9, 2), {"tile_qubits": 4, "low_qubits": 1}),
 ]
 
 # Where qsv_backward keeps psi and lambda in its workspace: psi right after the
