@@ -207,6 +207,39 @@ def pass_copies(plan, info, B, state, stats, torch, reps=3):
             "pass_ms_per_step": round(sum_pass, 3), "copy_over_pass": round(sum_copy / sum_pass, 4)}
 
 
+def graph_steps(plan, runs, g, state, E, gw, gx, steps, warmup, torch, binding):
+    """The same steps replayed from one captured HIP graph (qsv_graph_create):
+    every step copies its fresh weights and inputs into the captured buffers,
+    then launches the graph. Returns ms per step and the last step's
+    expectations, which must equal the eager step's on the same inputs."""
+    dev = state.device
+    B = state.shape[0]
+    wbuf = torch.empty_like(runs[0][0])
+    xbuf = torch.empty_like(runs[0][1])
+    Eg = torch.empty_like(E)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    graph = binding.StepGraph(plan, wbuf, xbuf, B, state, Eg, g, gw, gx, stream)
+    n = len(runs)
+    with torch.cuda.stream(stream):
+        for r in range(warmup):
+            wbuf.copy_(runs[r % n][0])
+            xbuf.copy_(runs[r % n][1])
+            graph.launch()
+    stream.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0.record(stream)
+        for r in range(warmup, warmup + steps):
+            wbuf.copy_(runs[r % n][0])
+            xbuf.copy_(runs[r % n][1])
+            graph.launch()
+        t1.record(stream)
+    stream.synchronize()
+    del graph
+    return t0.elapsed_time(t1) / steps, Eg
+
+
 def step_spread(ms_list):
     """Mean, min and standard deviation of per-step times (ms)."""
     import statistics
@@ -340,6 +373,11 @@ def main():
 
     ms, stats, step_ms = run_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch)
     spread = step_spread(step_ms)
+    E_eager = E.clone()
+    gms, E_graph = graph_steps(fused, runs, g, state, E, gw, gx, args.steps, args.warmup, torch, binding)
+    graph = {"ms_per_step": round(gms, 4), "evals_per_s": round(B / (gms / 1e3), 2),
+             "equals_eager": bool(torch.equal(E_graph, E_eager))}
+    log(args, f"[bench] fused, replayed from a HIP graph: {gms:.3f} ms/step")
     copy_gbs = copy_rate()["gbs"]  # on-box reference rate for HBM-bound kernels
     log(args, f"[bench] fused: {ms:.3f} ms/step")
     fam = families(stats)
@@ -465,6 +503,8 @@ def main():
                    "plan_ms": round(plan_ms, 2)},
         "per_gate": pg,
         "speedup_fused_vs_per_gate": round(pg["ms_per_step"] / ms, 2) if pg else None,
+        # the same steps replayed from one captured HIP graph (fresh inputs copied in)
+        "graph": graph,
         # per kernel (and per family of generated pass kernels): algorithmic GB/s,
         # as a fraction of the 8 TB/s peak and of the 1 GiB copy timed in this run
         "copy_gbs": copy_gbs,
