@@ -562,20 +562,54 @@ std::vector<std::pair<uint32_t, std::vector<int>>> group_stages(const std::vecto
     std::vector<std::pair<uint32_t, std::vector<int>>> stages;
     std::vector<int> remaining(units.size());
     for (size_t i = 0; i < units.size(); ++i) remaining[i] = (int)i;
-    while (!remaining.empty()) {
-        uint32_t R = 0, sD = 0, sC = 0;
-        std::vector<int> taken, skipped;
+    // One stage with register qubits `S`: in order, a unit joins when its dense
+    // qubits lie in S and it commutes with every unit left behind so far.
+    auto scan = [&](uint32_t S, std::vector<int>* taken, std::vector<int>* skipped) {
+        uint32_t sD = 0, sC = 0, R = 0;
+        int n = 0;
         for (int u : remaining) {
             const Unit& U = units[u];
-            if (!conflicts(U.D, U.C, sD, sC) && popc(R | U.D) <= kRegBits) {
+            if (!conflicts(U.D, U.C, sD, sC) && !(U.D & ~S)) {
                 R |= U.D;
-                taken.push_back(u);
+                ++n;
+                if (taken) taken->push_back(u);
             } else {
-                skipped.push_back(u);
                 sD |= U.D;
                 sC |= U.C;
+                if (skipped) skipped->push_back(u);
             }
         }
+        return std::make_pair(n, R);
+    };
+    while (!remaining.empty()) {
+        // Register qubits of the stage: of all kRegBits-subsets of the dense
+        // qubits still to come, the one that lets the most units join (every
+        // unit needs at most kRegBits dense qubits, so some unit always joins);
+        // ties keep the first subset in enumeration order.
+        uint32_t pool = 0;
+        for (int u : remaining) pool |= units[u].D;
+        std::vector<int> bits;
+        for (int q = 0; q < 32; ++q)
+            if (pool >> q & 1) bits.push_back(q);
+        const int k = std::min<int>(kRegBits, (int)bits.size());
+        uint32_t bestS = 0;
+        int bestN = -1;
+        std::vector<int> idx(k);
+        for (int i = 0; i < k; ++i) idx[i] = i;
+        while (true) {
+            uint32_t S = 0;
+            for (int i : idx) S |= 1u << bits[i];
+            const int n = scan(S, nullptr, nullptr).first;
+            if (n > bestN) { bestN = n; bestS = S; }
+            // next k-combination of bits
+            int i = k - 1;
+            while (i >= 0 && idx[i] == (int)bits.size() - k + i) --i;
+            if (i < 0) break;
+            ++idx[i];
+            for (int j = i + 1; j < k; ++j) idx[j] = idx[j - 1] + 1;
+        }
+        std::vector<int> taken, skipped;
+        const uint32_t R = scan(bestS, &taken, &skipped).second;
         stages.emplace_back(R, taken);
         remaining = skipped;
     }
