@@ -3,7 +3,9 @@
 // Kernels (all float32 amplitude arithmetic, float64 reductions):
 //   k_coef          gate-matrix cache evaluation: C + cos(t/2) A + sin(t/2) S per
 //                   gate (Eq. (1) generalised), products of fused chains, daggers
-//   k_init          product-state init from the leading 1-qubit gates (embedding)
+//   k_init          product-state init from the leading 1-qubit gates (embedding),
+//                   for the per-gate method (the fused passes build it in their
+//                   first pass instead)
 //   k_pg_apply      plain method: one strided sweep of the state per gate
 //   k_pg_adj        plain method, backward: gradient partial + uncompute psi, lambda
 //   k_pg_apply_vec / k_pg_adj_vec   the same with 16-byte streaming accesses (complex64)
@@ -14,6 +16,7 @@
 //   k_grad_reduce   gradient partials -> weight (batch-summed) and input gradients
 //   k_multi_fwd / k_multi_bwd, k_init_multi, k_expval_part_multi / k_expval_final_multi
 //                   many circuits in one plan: fused passes as one launch per round
+//                   (k_init_multi only when some circuit has no forward pass)
 //   k_pass_copy     measurement aid: a generated pass's loads and stores alone
 // The fused passes of single-circuit plans normally run as kernels generated
 // for the plan (jit.cpp); k_pass_fwd / k_pass_bwd interpret the same tables.
@@ -915,6 +918,32 @@ __device__ __forceinline__ void g_store(float2* st, const Lay& L, const float2 (
     }
 }
 
+// The product state at a thread's 16 amplitudes, in place of loading them
+// (first forward pass): amp(idx) = prod over amplitude bits s of
+// v_{W-1-s}[bit s of idx], v_q = column 0 of qubit q's prefix matrix. The
+// factors of the thread's fixed bits (L.gT) are multiplied once, then the
+// product is split over the four register bits.
+__device__ __forceinline__ void init_regs(const Lay& L, float2 (&a)[kRegs], const int32_t* __restrict__ pm,
+                                          const float* __restrict__ mats, int W, int b, int n_shared,
+                                          int n_ps) {
+    const int rm = L.gr[0] | L.gr[1] | L.gr[2] | L.gr[3];
+    float2 P = make_float2(1.f, 0.f);
+    for (int s = 0; s < W; ++s)
+        if (!((rm >> s) & 1)) P = cmul(P, prefix_v(mats, pm, W - 1 - s, (L.gT >> s) & 1, b, n_shared, n_ps));
+    a[0] = P;
+#pragma unroll
+    for (int p = 0; p < kRegBits; ++p) {
+        const int q = W - 1 - (31 - __builtin_clz((unsigned)L.gr[p]));
+        const float2 v0 = prefix_v(mats, pm, q, 0, b, n_shared, n_ps);
+        const float2 v1 = prefix_v(mats, pm, q, 1, b, n_shared, n_ps);
+#pragma unroll
+        for (int k = 0; k < (1 << p); ++k) {
+            a[k | (1 << p)] = cmul(a[k], v1);
+            a[k] = cmul(a[k], v0);
+        }
+    }
+}
+
 // --- register ops, templated on the target's register position P ---
 template <int P, bool CTL>
 __device__ __forceinline__ void r_u2(float2 (&a)[kRegs], const M2& M, int cm) {
@@ -1210,8 +1239,9 @@ __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
                                               const DOp* __restrict__ O,
                                               const DTerm* __restrict__ Tm,
                                               const float* __restrict__ mats, int n_shared,
-                                              int n_ps, float2* __restrict__ st, int W, int b,
-                                              int64_t tis, float2* lds) {
+                                              int n_ps, const int32_t* __restrict__ pm,
+                                              float2* __restrict__ st, int W, int b, int64_t tis,
+                                              float2* lds) {
     const int m = P->m;
     const int t = threadIdx.x;
     const bool act = t < (1 << (m - kRegBits));
@@ -1222,8 +1252,9 @@ __device__ __forceinline__ void pass_fwd_tile(const DPass* __restrict__ P,
     Lay L;
     make_layout(P, m, cur, t, base, L);
     float2 a[kRegs];
-    if (act) g_load(st, L, a);
-    else for (int k = 0; k < kRegs; ++k) a[k] = make_float2(0.f, 0.f);
+    if (!act) for (int k = 0; k < kRegs; ++k) a[k] = make_float2(0.f, 0.f);
+    else if (P->flags & PF_INIT_FWD) init_regs(L, a, pm, mats, W, b, n_shared, n_ps);
+    else g_load(st, L, a);
 
     for (int s = 0; s < P->n_stages; ++s) {
         const DStage& stg = S[P->stage0 + s];
@@ -1438,13 +1469,14 @@ __global__ __launch_bounds__(1024) void k_pass_fwd(const DPass* __restrict__ P,
                                                    const DOp* __restrict__ O,
                                                    const DTerm* __restrict__ Tm,
                                                    const float* __restrict__ mats, int n_shared,
-                                                   int n_ps, float2* __restrict__ state, int W) {
+                                                   int n_ps, const int32_t* __restrict__ pm,
+                                                   float2* __restrict__ state, int W) {
     extern __shared__ float2 lds[];
     const int tbits = W - P->m;
     const int64_t tile = blockIdx.x;
     const int b = (int)(tile >> tbits);
     const int64_t tis = tile & ((int64_t(1) << tbits) - 1);
-    pass_fwd_tile(P, S, O, Tm, mats, n_shared, n_ps, state + ((size_t)b << W), W, b, tis, lds);
+    pass_fwd_tile(P, S, O, Tm, mats, n_shared, n_ps, pm, state + ((size_t)b << W), W, b, tis, lds);
 }
 
 __global__ __launch_bounds__(256) void k_pass_bwd(
@@ -1474,14 +1506,14 @@ __global__ __launch_bounds__(256) void k_multi_fwd(
     const DCirc* __restrict__ C, const DItem* __restrict__ Q,
     const DPass* __restrict__ passes, const DStage* __restrict__ S, const DOp* __restrict__ O,
     const DTerm* __restrict__ Tm, const float* __restrict__ mats, int n_shared, int n_ps,
-    float2* __restrict__ state, int64_t row) {
+    const int32_t* __restrict__ pm, float2* __restrict__ state, int64_t row) {
     extern __shared__ float2 lds[];
     const DItem I = Q[blockIdx.x];
     const DCirc& c = C[I.c];
     const int tbits = c.W - c.m;
     const int b = I.tile >> tbits;
     const int64_t tis = I.tile & ((1 << tbits) - 1);
-    pass_fwd_tile(passes + c.fwd0 + I.pass, S, O, Tm, mats, n_shared, n_ps,
+    pass_fwd_tile(passes + c.fwd0 + I.pass, S, O, Tm, mats, n_shared, n_ps, pm + c.pm0,
                   state + (size_t)b * row + c.amp0, c.W, b, tis, lds);
 }
 
@@ -2405,16 +2437,25 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
         DeviceTables::Queue* Q;
         if ((rc = get_queue(p, T, B, &Q))) return rc;
         const double amps = (double)B * (double)p->row;
-        hipEvent_t ev = prof_begin(p, s);
-        hipLaunchKernelGGL(k_init_multi, dim3((unsigned)p->nchunk_tot, (unsigned)B), dim3(256), 0, s,
-                           (const DCirc*)T->circ, (int)p->circ.size(), st, p->row, T->prefix_mat,
-                           (const float*)mats, p->n_shared_mats, p->n_ps_mats);
-        prof_end(p, s, ev, K_INIT, 8.0 * amps, 0.0);
+        // each circuit's first pass builds its product state, unless a
+        // circuit has no forward pass at all
+        bool all_init = true;
+        for (const DCirc& c : p->circ)
+            all_init = all_init && c.n_fwd > 0 && (p->fwd_pass[c.fwd0].flags & PF_INIT_FWD);
+        hipEvent_t ev;
+        if (!all_init) {
+            ev = prof_begin(p, s);
+            hipLaunchKernelGGL(k_init_multi, dim3((unsigned)p->nchunk_tot, (unsigned)B), dim3(256), 0, s,
+                               (const DCirc*)T->circ, (int)p->circ.size(), st, p->row, T->prefix_mat,
+                               (const float*)mats, p->n_shared_mats, p->n_ps_mats);
+            prof_end(p, s, ev, K_INIT, 8.0 * amps, 0.0);
+        }
         double flops = 0.0, bytes = 0.0;
         for (const DCirc& c : p->circ)
             for (int r = 0; r < c.n_fwd; ++r) {
                 flops += p->fwd_pass_flops[c.fwd0 + r] * (double)B * (double)(int64_t(1) << c.W);
-                bytes += 16.0 * (double)B * (double)(int64_t(1) << c.W);
+                const bool init = p->fwd_pass[c.fwd0 + r].flags & PF_INIT_FWD;
+                bytes += (init ? 8.0 : 16.0) * (double)B * (double)(int64_t(1) << c.W);
             }
         ev = prof_begin(p, s);
         for (size_t r = 0; r + 1 < Q->fwd_rounds.size(); ++r) {
@@ -2422,14 +2463,16 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
             hipLaunchKernelGGL(k_multi_fwd, dim3((unsigned)n), dim3(256), multi_lds(p), s,
                                (const DCirc*)T->circ, (const DItem*)(Q->fwd + i0), (const DPass*)T->fwd_pass,
                                (const DStage*)T->stages, (const DOp*)T->ops, (const DTerm*)T->terms,
-                               (const float*)mats, p->n_shared_mats, p->n_ps_mats, st, p->row);
+                               (const float*)mats, p->n_shared_mats, p->n_ps_mats, T->prefix_mat, st, p->row);
         }
         prof_end(p, s, ev, K_MULTI_FWD, bytes, flops);
         HIP_TRY(hipGetLastError());
         return QSV_OK;
     }
-    // generated forward kernels build the product state in their first pass
-    const bool fused_init = !T->fwd_fn.empty() && !p->fwd_pass.empty() && (p->fwd_pass[0].flags & PF_INIT_FWD);
+    // fused passes (generated or table-driven) build the product state in
+    // their first pass
+    const bool fused_init = p->opts.method != QSV_METHOD_PER_GATE && !p->fwd_pass.empty() &&
+                            (p->fwd_pass[0].flags & PF_INIT_FWD);
     if (!fused_init && (rc = run_init(p, T, mats, B, st, s))) return rc;
     const int W = p->W;
     const double amps = (double)B * (double)(int64_t(1) << W);
@@ -2480,7 +2523,7 @@ static int forward_impl(const qsv_plan_t* p, const float* w, const float* x, int
         } else {
             hipLaunchKernelGGL(k_pass_fwd, dim3(tiles), dim3(threads), lds, s, T->fwd_pass + i,
                                T->stages, T->ops, T->terms, (const float*)mats, p->n_shared_mats,
-                               p->n_ps_mats, st, W);
+                               p->n_ps_mats, T->prefix_mat, st, W);
         }
         // a first pass that builds the initial state reads nothing; a last pass
         // with the readout adds its partials
@@ -2992,12 +3035,19 @@ int qsv_plan_estimate(const qsv_plan_t* p, int64_t B, double hbm_gbs, double alu
     auto sweep = [&](double bytes, double flops) { return std::max(bytes / bw, flops / alu); };
     double t = 0.0;
     int64_t launches = 3;  // coefficients, init, readout
+    // a first fused pass that builds the product state replaces the init
+    // launch and reads nothing
+    auto fwd_bytes = [&](const DPass& ps) { return (ps.flags & PF_INIT_FWD) ? 8.0 : 16.0; };
     if (p->multi) {
         int nf = 0, nb = 0;
+        bool all_init = true;
         for (const DCirc& c : p->circ) {
             const double a = (double)B * (double)(int64_t(1) << c.W);
-            t += sweep(8.0 * a, 0.0) + sweep(8.0 * a, 0.0);  // init + readout
-            for (int r = 0; r < c.n_fwd; ++r) t += sweep(16.0 * a, p->fwd_pass_flops[c.fwd0 + r] * a);
+            const bool init = c.n_fwd > 0 && (p->fwd_pass[c.fwd0].flags & PF_INIT_FWD);
+            all_init = all_init && init;
+            t += (init ? 0.0 : sweep(8.0 * a, 0.0)) + sweep(8.0 * a, 0.0);  // init + readout
+            for (int r = 0; r < c.n_fwd; ++r)
+                t += sweep(fwd_bytes(p->fwd_pass[c.fwd0 + r]) * a, p->fwd_pass_flops[c.fwd0 + r] * a);
             for (int r = 0; r < c.n_bwd; ++r) {
                 const int fl = p->bwd_pass[c.bwd0 + r].flags;
                 const double pa = ((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0);
@@ -3006,11 +3056,14 @@ int qsv_plan_estimate(const qsv_plan_t* p, int64_t B, double hbm_gbs, double alu
             nf = std::max(nf, c.n_fwd);
             nb = std::max(nb, c.n_bwd);
         }
-        launches += nf + nb + 2;
+        launches += nf + nb + 2 - (all_init ? 1 : 0);
     } else {
         const double a = (double)B * (double)(int64_t(1) << p->W);
         const double e = (double)amp_size(p);  // bytes per amplitude
-        t += 2.0 * sweep(e * a, 0.0);  // init + readout
+        const bool init = p->opts.method != QSV_METHOD_PER_GATE && !p->fwd_pass.empty() &&
+                          (p->fwd_pass[0].flags & PF_INIT_FWD);
+        t += (init ? 0.0 : sweep(e * a, 0.0)) + sweep(e * a, 0.0);  // init + readout
+        if (init) --launches;
         if (p->opts.method == QSV_METHOD_PER_GATE) {
             t += sweep(3.0 * e * a, 0.0);  // adjoint init
             for (size_t i = 0; i < p->pg_fwd.size(); ++i) {
@@ -3025,7 +3078,8 @@ int qsv_plan_estimate(const qsv_plan_t* p, int64_t B, double hbm_gbs, double alu
             }
             launches += (int64_t)(p->pg_fwd.size() + p->pg_bwd.size()) + 2;
         } else {
-            for (size_t i = 0; i < p->fwd_pass.size(); ++i) t += sweep(16.0 * a, p->fwd_pass_flops[i] * a);
+            for (size_t i = 0; i < p->fwd_pass.size(); ++i)
+                t += sweep(fwd_bytes(p->fwd_pass[i]) * a, p->fwd_pass_flops[i] * a);
             for (size_t i = 0; i < p->bwd_pass.size(); ++i) {
                 const int fl = p->bwd_pass[i].flags;
                 const double pa = ((fl & PF_FIRST_BWD) ? 8.0 : 16.0) + ((fl & PF_LAST_BWD) ? 0.0 : 16.0);
