@@ -53,6 +53,10 @@ def parse():
                     help="timed steps of the 512-circuit uneven set (0 = skip)")
     ap.add_argument("--pass-copy", type=int, choices=(0, 1), default=1,
                     help="time each generated pass's loads and stores alone (qsv_pass_copy)")
+    ap.add_argument("--launch-log", default=None,
+                    help="after the per-gate steps, run one more with one profile record per "
+                         "launch and write the records (kernel.class, bytes, ms) here as JSON, "
+                         "for matching per-dispatch counters to gate classes")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: time a plain 1 GiB device copy (counter calibration)")
@@ -322,7 +326,10 @@ def bench_uneven(args, torch, dev, binding, inputs):
            "alg_gbs": round(step_bytes / (gms / 1e3) / 1e9, 1),
            "opts": opts_summary(tr["opts"]), "tune_seconds": tr["seconds"], "plan_ms": round(plan_ms, 1),
            "graph_equals_eager": same,
-           "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3)}
+           # per kernel over the profiled steps: time, and algorithmic rates
+           "kernels": {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                           "tflops": round(v["flops"] / (v["total_ms"] * 1e9), 2) if v["total_ms"] > 0 else None,
+                           "gbs": round(v["bytes"] / (v["total_ms"] * 1e6), 1) if v["total_ms"] > 0 else None}
                        for k, v in stats.items()}}
     log(args, f"[bench] uneven: {out}")
     return out
@@ -414,6 +421,17 @@ def main():
                               "copy_frac": round(v["bytes"] / (v["total_ms"] / 1e3) / 1e9 / copy_gbs, 4)}
                           for k, v in sorted(pstats.items()) if v["total_ms"] > 0}}
         log(args, f"[bench] per-gate: {pms:.3f} ms/step  {pg}")
+        if args.launch_log:
+            w, x = runs[0]
+            per_gate.profile(2)
+            per_gate.profile_launches()
+            per_gate.forward_expval(w, x, B, state, E)
+            per_gate.backward(w, x, state, g, gw=gw, gx=gx)
+            torch.cuda.synchronize()
+            launches = per_gate.profile_launches()
+            per_gate.profile(False)
+            with open(args.launch_log, "w") as f:
+                json.dump({"workload": args.workload, "method": "per_gate", "launches": launches}, f)
 
     uneven = bench_uneven(args, torch, dev, binding, inputs) if args.uneven_steps > 0 else None
     copies = pass_copies(fused, info, B, state, stats, torch) if args.pass_copy else None

@@ -457,8 +457,11 @@ int qsv_pass_copy(const qsv_plan_t* plan, int32_t which, int32_t pass, int64_t b
  * "qsv_b<i>"); the per-gate method's kernels one entry per gate class
  * ("k_pg_apply.1q", ".diag", ".ctl" for controlled gates, ".sign" for CZ / Z /
  * CCZ; likewise "k_pg_adj.*"); other library kernels one entry per kernel.
- * Enabling or reading while another thread calls into the same plan is not
- * supported.
+ * With on = 2 the record is not summed: qsv_profile_read writes one entry
+ * per launch (launches = 1) in launch order, under the same names, so that
+ * per-dispatch counters of an external profiler can be matched to gate
+ * classes. on outside 0..2 is QSV_ERR_ARG. Enabling or reading while another
+ * thread calls into the same plan is not supported.
  */
 typedef struct {
     char name[32];

@@ -364,7 +364,8 @@ class StepGraph:
 
 
 def qsv_profile_enable(h, on):
-    return _check(lib().qsv_profile_enable(h, int(bool(on))))
+    """on: False / 0 off, True / 1 per-kernel totals, 2 one record per launch."""
+    return _check(lib().qsv_profile_enable(h, 2 if on == 2 else int(bool(on))))
 
 
 def qsv_profile_read(h, max_out=512):
@@ -375,6 +376,16 @@ def qsv_profile_read(h, max_out=512):
     return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
                                    "bytes": arr[i].bytes, "flops": arr[i].flops}
             for i in range(n.value)}
+
+
+def qsv_profile_read_launches(h, max_out=1 << 16):
+    """Records of the per-launch mode (profile enabled with 2), in launch order:
+    [{name, ms, bytes, flops}]."""
+    arr = (qsv_kernel_stat * max_out)()
+    n = ctypes.c_int32()
+    _check(lib().qsv_profile_read(h, arr, max_out, ctypes.byref(n)))
+    return [{"name": arr[i].name.decode(), "ms": arr[i].total_ms, "bytes": arr[i].bytes,
+             "flops": arr[i].flops} for i in range(n.value)]
 
 
 def qsv_strerror(code):
@@ -456,6 +467,9 @@ class Plan:
 
     def profile_read(self):
         return qsv_profile_read(self.handle)
+
+    def profile_launches(self):
+        return qsv_profile_read_launches(self.handle)
 
     def workspace(self, batch, op, device):
         """Workspace of kind `op` for the current stream on `device`: calls on

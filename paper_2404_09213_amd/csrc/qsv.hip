@@ -1750,6 +1750,7 @@ struct ProfRec {
 
 struct Profiler {
     bool on = false;
+    bool each = false;  // one entry per launch, in launch order
     std::mutex mu;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
@@ -3189,7 +3190,9 @@ int qsv_profile_enable(qsv_plan_t* p, int32_t on) {
         if (!pr) { set_error("profiler allocation failed"); return QSV_ERR_OOM; }
         p->prof = pr;
     }
+    if (on < 0 || on > 2) { set_error("profile mode must be 0, 1 or 2"); return QSV_ERR_ARG; }
     prof_of(p)->on = on != 0;
+    prof_of(p)->each = on == 2;
     return QSV_OK;
 }
 
@@ -3197,19 +3200,22 @@ int qsv_profile_read(qsv_plan_t* p, qsv_kernel_stat* out, int32_t max_out, int32
     int rc = check_plan(p);
     if (rc) return rc;
     if (!n_out || (max_out > 0 && !out)) { set_error("null pointer"); return QSV_ERR_ARG; }
-    // totals per (kernel, generated pass); ordered by kernel id, then pass
+    // totals per (kernel, generated pass); ordered by kernel id, then pass.
+    // Per-launch mode keys each record by its position instead.
     std::map<std::pair<int, int>, qsv_kernel_stat> tot;
     Profiler* pr = prof_of(p);
     int err = QSV_OK;
     if (pr) {
         std::lock_guard<std::mutex> lk(pr->mu);
+        int pos = 0;
         for (auto& r : pr->recs) {
+            const std::pair<int, int> key = pr->each ? std::make_pair(pos++, 0) : std::make_pair(r.kid, r.sub);
             float ms = 0.f;
             if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
                 set_error("event timing failed");
                 err = QSV_ERR_HIP;
             }
-            auto it = tot.find({r.kid, r.sub});
+            auto it = tot.find(key);
             if (it == tot.end()) {
                 qsv_kernel_stat z;
                 std::memset(&z, 0, sizeof z);
@@ -3219,7 +3225,7 @@ int qsv_profile_read(qsv_plan_t* p, qsv_kernel_stat* out, int32_t max_out, int32
                     std::snprintf(z.name, sizeof z.name, "qsv_%c%d", r.kid == K_PASS_FWD ? 'f' : 'b', r.sub);
                 else
                     std::snprintf(z.name, sizeof z.name, "%s", kKernelNames[r.kid]);
-                it = tot.emplace(std::make_pair(r.kid, r.sub), z).first;
+                it = tot.emplace(key, z).first;
             }
             it->second.launches++;
             it->second.total_ms += ms;

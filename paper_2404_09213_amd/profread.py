@@ -12,6 +12,11 @@
     python -m paper_2404_09213_amd.profread traffic_all FETCH_DIR WRITE_DIR COPY_FETCH_DIR \\
             COPY_WRITE_DIR COPY_BYTES KERNEL_REGEX
         the same for every kernel matching KERNEL_REGEX
+    python -m paper_2404_09213_amd.profread per_gate FETCH_DIR WRITE_DIR COPY_FETCH_DIR \
+            COPY_WRITE_DIR COPY_BYTES LAUNCH_LOG
+        HBM bytes of every launch of one per-gate step, matched to the gate
+        class of the launch from bench.py's --launch-log file, and summed per
+        class against the algorithmic bytes; prints JSON
     python -m paper_2404_09213_amd.profread util SQ_DIR [KERNEL_REGEX]
         per kernel from one SQ + GRBM counter pass: vector and matrix
         instructions per wave, matrix-core busy fraction, vector
@@ -139,6 +144,67 @@ def traffic_all(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes
             "traffic_by_kernel": {k: round(v, 1) for k, v in sorted(out.items())}}
 
 
+def dispatches(d, counter):
+    """[(short kernel name, value)] of one counter, in dispatch order."""
+    rows = []
+    with open(_one(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), short(r["Kernel_Name"]), float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def _base(name):
+    """Kernel family of a dispatch or of a library record: 'k_pg_adj_vec',
+    'k_pg_adj<float2>' and 'k_pg_adj.sign' all give 'k_pg_adj'."""
+    n = name.split(".")[0].split("<")[0]
+    return n[:-4] if n.endswith("_vec") else n
+
+
+def _match_last(disp, want):
+    """Index in disp (library kernels only, in order) where the last run of
+    the families in want starts."""
+    fam = [_base(k) for k, _ in disp]
+    n = len(want)
+    for i in range(len(fam) - n, -1, -1):
+        if fam[i:i + n] == want:
+            return i
+    raise ValueError("the launch log's kernel sequence does not occur in the counter dispatches")
+
+
+def per_gate(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, launch_log):
+    """Per-launch HBM bytes (FETCH_SIZE, WRITE_SIZE scaled as in traffic())
+    of the last per-gate step in the two counter runs, with each launch's gate
+    class and algorithmic bytes from the library's per-launch record of the
+    same step (bench.py --launch-log), and the per-class sums."""
+    with open(launch_log) as f:
+        log = json.load(f)["launches"]
+    want = [_base(r["name"]) for r in log]
+    fetch_scale = copy_bytes / (_copy_kib(copy_fetch_dir, "FETCH_SIZE") * 1024.0)
+    write_scale = copy_bytes / (_copy_kib(copy_write_dir, "WRITE_SIZE") * 1024.0)
+    runs = []
+    for d, c, sc in ((fetch_dir, "FETCH_SIZE", fetch_scale), (write_dir, "WRITE_SIZE", write_scale)):
+        disp = [(k, v) for k, v in dispatches(d, c) if k.startswith("k_")]
+        i = _match_last(disp, want)
+        runs.append([v * 1024.0 * sc for _, v in disp[i:i + len(want)]])
+    launches, classes = [], {}
+    for r, fb, wb in zip(log, runs[0], runs[1]):
+        launches.append({"name": r["name"], "alg_bytes": r["bytes"], "fetch_bytes": round(fb, 1),
+                         "write_bytes": round(wb, 1)})
+        c = classes.setdefault(r["name"], {"launches": 0, "alg_bytes": 0.0, "fetch_bytes": 0.0,
+                                           "write_bytes": 0.0})
+        c["launches"] += 1
+        c["alg_bytes"] += r["bytes"]
+        c["fetch_bytes"] += fb
+        c["write_bytes"] += wb
+    for c in classes.values():
+        c["traffic_over_alg"] = round((c["fetch_bytes"] + c["write_bytes"]) / c["alg_bytes"], 3) \
+            if c["alg_bytes"] > 0 else None
+    return {"fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+            "classes": dict(sorted(classes.items())), "launches": launches}
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         rows = sorted(kernel_stats(argv[1]), key=lambda r: -r["total_us"])
@@ -155,6 +221,9 @@ def main(argv):
         print(json.dumps(util(argv[1], argv[2] if len(argv) > 2 else None), indent=1))
     elif len(argv) == 7 and argv[0] == "traffic_all":
         print(json.dumps(traffic_all(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6]), indent=1))
+    elif len(argv) == 7 and argv[0] == "per_gate":
+        r = per_gate(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6])
+        print(json.dumps({k: v for k, v in r.items() if k != "launches"}, indent=1))
     elif len(argv) == 7 and argv[0] == "traffic":
         print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], float(argv[5]), argv[6])))
     else:
