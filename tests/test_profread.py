@@ -66,3 +66,53 @@ def test_profile_modes_are_checked():
     p.profile(2)
     assert p.profile_launches() == []   # nothing launched yet
     p.profile(False)
+
+
+@pytest.mark.gpu
+def test_per_launch_records_match_the_totals():
+    """Mode 2 gives one record per launch, in launch order, that sums to the
+    per-kernel totals of mode 1 for the same step."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    c = inputs.rx_ry_rz_cz_ladder(8, 2)
+    B = 4
+    p = binding.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs, method="per_gate")
+    w, x = inputs.draw_angles(c, B, 5)
+    wt = torch.from_numpy(w).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    g = torch.ones((B, c.n_qubits), dtype=torch.float64, device=dev)
+
+    def step():
+        st, E = p.forward_expval(wt, xt, B)
+        p.backward(wt, xt, st, g)
+        torch.cuda.synchronize()
+
+    print("[profile] per-gate ladder 8 qubits, batch 4", flush=True)
+    step()
+    p.profile(True)
+    p.profile_read()
+    step()
+    tot = p.profile_read()
+    p.profile(2)
+    step()
+    recs = p.profile_launches()
+    p.profile(False)
+    assert recs and recs[0]["name"] == "k_coef"
+    per = collections.defaultdict(lambda: [0, 0.0])
+    for r in recs:
+        per[r["name"]][0] += 1
+        per[r["name"]][1] += r["bytes"]
+        assert r["ms"] >= 0.0
+    assert set(per) == set(tot)
+    for k, v in tot.items():
+        assert per[k][0] == v["launches"], k
+        assert per[k][1] == pytest.approx(v["bytes"], rel=1e-12), k
+    # forward gate launches come before every adjoint launch
+    names = [r["name"] for r in recs]
+    last_fwd = max(i for i, n in enumerate(names) if n.startswith("k_pg_apply"))
+    first_adj = min(i for i, n in enumerate(names) if n.startswith("k_pg_adj"))
+    assert last_fwd < first_adj
