@@ -60,7 +60,10 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: time a plain 1 GiB device copy (counter calibration)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.launch_log and args.per_gate_steps <= 0:
+        ap.error("--launch-log needs --per-gate-steps > 0")
+    return args
 
 
 def copy_rate(reps=5):

@@ -384,6 +384,8 @@ def qsv_profile_read_launches(h, max_out=1 << 16):
     arr = (qsv_kernel_stat * max_out)()
     n = ctypes.c_int32()
     _check(lib().qsv_profile_read(h, arr, max_out, ctypes.byref(n)))
+    if n.value >= max_out:
+        raise RuntimeError(f"more than {max_out - 1} launches recorded: read more often or raise max_out")
     return [{"name": arr[i].name.decode(), "ms": arr[i].total_ms, "bytes": arr[i].bytes,
              "flops": arr[i].flops} for i in range(n.value)]
 
