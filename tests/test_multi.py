@@ -261,6 +261,33 @@ def test_multi_small_mixed(orc):
     _run_multi(_mixed_set(11, 9, 4, 13), 2, 11, orc)
 
 
+def _product_circuit():
+    # only 1-qubit gates: the whole circuit folds into the initial product
+    # state, so its plan has no forward pass to build that state in
+    c = I.Circuit(5, name="product_only")
+    for q in range(5):
+        c.weight("RY", q)
+    c.weight("RZ", 2)
+    c.input("RX", 4, 0)
+    return c
+
+
+def test_product_only_circuit_has_no_forward_pass():
+    c = _product_circuit()
+    p = B.Plan(c.n_qubits, c.gates, c.n_weights, c.n_inputs)
+    assert p.info()["n_fwd_passes"] == 0
+
+
+@pytest.mark.gpu
+def test_multi_with_a_circuit_without_forward_passes(orc):
+    # one circuit without a forward pass makes the plan initialise every
+    # state with the separate init launch; the others' first passes then
+    # rebuild theirs, and every result must still match the oracle
+    cs = _mixed_set(15, 4, 4, 10)
+    cs.insert(2, _product_circuit())
+    _run_multi(cs, 2, 15, orc)
+
+
 @pytest.mark.gpu
 def test_multi_controlled_kinds(orc):
     rng = np.random.default_rng(13)
